@@ -1,0 +1,787 @@
+// C ABI of libstats.so: handles, argument checks, streams, staging and the
+// order of kernel launches.  Every arithmetic step runs in the kernels of
+// accum.hip / merge.hip / finalize.hip (and the wide, segmented and text
+// kernels); this file only moves bytes and sequences work.
+#include <algorithm>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "common.hpp"
+#include "runtime.hpp"
+
+using namespace st;
+
+namespace st {
+
+thread_local std::string g_err;
+
+int fail(int code, const std::string& msg) {
+  g_err = msg;
+  return code;
+}
+
+int hip_fail(stats_ctx* h, hipError_t e, const char* what) {
+  if (h) h->poisoned = true;
+  g_err = std::string(what) + ": " + hipGetErrorString(e);
+  return STATS_E_HIP;
+}
+
+DeviceGuard::DeviceGuard(int dev) {
+  if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+  ok = hipSetDevice(dev) == hipSuccess;
+}
+DeviceGuard::~DeviceGuard() {
+  if (prev >= 0) (void)hipSetDevice(prev);
+}
+
+int elem_size(int dtype) {
+  switch (dtype) {
+    case STATS_I32: return 4;
+    case STATS_F32: return 4;
+    case STATS_I64: return 8;
+    case STATS_F64: return 8;
+    default: return 0;
+  }
+}
+
+bool is_int_col(const stats_column& c) {
+  return c.dtype == STATS_I32 || c.dtype == STATS_I64 || (c.flags & STATS_COL_INTEGER);
+}
+
+// Device allocation that reports STATS_E_NOMEM; grows *cap_bytes if needed.
+int ensure_dev(stats_ctx* h, void** ptr, size_t* cap, size_t need) {
+  if (*cap >= need && *ptr) return STATS_OK;
+  if (*ptr) {
+    hipError_t e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+    (void)hipFree(*ptr);
+    *ptr = nullptr;
+    *cap = 0;
+  }
+  if (std::getenv("STATS_FAIL_ALLOC")) return fail(STATS_E_NOMEM, "allocation refused (STATS_FAIL_ALLOC)");
+  hipError_t e = hipMalloc(ptr, need);
+  if (e != hipSuccess) {
+    (void)hipGetLastError();
+    *ptr = nullptr;
+    return fail(STATS_E_NOMEM, "hipMalloc of " + std::to_string(need) + " bytes failed");
+  }
+  *cap = need;
+  return STATS_OK;
+}
+
+void Timer::begin(stats_ctx* h, int which, hipStream_t s) {
+  if (!(h->flags & STATS_CFG_TIMING)) return;
+  hipEvent_t a, b;
+  (void)hipEventCreate(&a);
+  (void)hipEventCreate(&b);
+  s_ = s ? s : h->stream;
+  (void)hipEventRecord(a, s_);
+  h_ = h;
+  which_ = which;
+  a_ = a;
+  b_ = b;
+}
+
+void Timer::end() {
+  if (!h_) return;
+  (void)hipEventRecord(b_, s_);
+  h_->pending[which_].push_back({a_, b_});
+  h_ = nullptr;
+}
+
+void collect_timings(stats_ctx* h) {
+  for (int k = 0; k < STATS_K_COUNT; ++k) {
+    for (auto& pr : h->pending[k]) {
+      float ms = 0.f;
+      if (hipEventElapsedTime(&ms, pr.first, pr.second) == hipSuccess) {
+        h->kt_ms[k] += ms;
+        h->kt_n[k] += 1;
+      }
+      (void)hipEventDestroy(pr.first);
+      (void)hipEventDestroy(pr.second);
+    }
+    h->pending[k].clear();
+  }
+}
+
+int check_status(stats_ctx* h) {
+  DevStatus s;
+  hipError_t e = hipMemcpy(&s, h->status_dev, sizeof s, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpy(status)");
+  if (s.bits & ST_PARSE) {
+    char buf[128];
+    snprintf(buf, sizeof buf, "malformed text field at byte offset %llu",
+             (unsigned long long)s.parse_off);
+    return fail(STATS_E_PARSE, buf);
+  }
+  if (s.bits & ST_INEXACT)
+    return fail(STATS_E_INEXACT,
+                "an integer column left the exact range (non-integer value, |x - shift|^2 sum "
+                ">= 2^53 in a block, or |value| >= 2^40)");
+  return STATS_OK;
+}
+
+int sync_handle(stats_ctx* h) {
+  hipError_t e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize");
+  if (h->copy_stream) {
+    e = hipStreamSynchronize(h->copy_stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamSynchronize(copy)");
+  }
+  collect_timings(h);
+  return check_status(h);
+}
+
+}  // namespace st
+
+// ---------------------------------------------------------------------------
+// open / close
+
+static int validate_cfg(const stats_config* cfg) {
+  if (!cfg) return fail(STATS_E_ARG, "cfg is NULL");
+  if (cfg->p < 1 || cfg->p > STATS_MAX_P) return fail(STATS_E_ARG, "p must be in 1..1024");
+  if (!cfg->cols) return fail(STATS_E_ARG, "cols is NULL");
+  if (cfg->n_planes < 1 || cfg->n_planes > STATS_MAX_PLANES)
+    return fail(STATS_E_ARG, "n_planes must be in 1..32");
+  for (int k = 0; k < cfg->n_planes; ++k)
+    if (cfg->row_stride[k] <= 0) return fail(STATS_E_ARG, "row_stride must be positive");
+  for (int c = 0; c < cfg->p; ++c) {
+    const stats_column& col = cfg->cols[c];
+    const int es = elem_size(col.dtype);
+    if (!es) return fail(STATS_E_ARG, "column " + std::to_string(c) + ": unknown dtype");
+    if (col.plane < 0 || col.plane >= cfg->n_planes)
+      return fail(STATS_E_ARG, "column " + std::to_string(c) + ": plane out of range");
+    if (col.byte_offset < 0 || col.byte_offset + es > cfg->row_stride[col.plane])
+      return fail(STATS_E_ARG, "column " + std::to_string(c) + ": element outside the row stride");
+    if (col.byte_offset % es != 0)
+      return fail(STATS_E_ARG, "column " + std::to_string(c) + ": misaligned byte_offset");
+    if (col.flags & ~(uint32_t)(STATS_COL_INTEGER | STATS_COL_IDENTIFIER))
+      return fail(STATS_E_ARG, "column " + std::to_string(c) + ": unknown flags");
+  }
+  if (cfg->precision < STATS_PREC_FP64 || cfg->precision > STATS_PREC_AUTO)
+    return fail(STATS_E_ARG, "unknown precision");
+  if (cfg->block_rows < 0 || (cfg->block_rows % 1024) != 0)
+    return fail(STATS_E_ARG, "block_rows must be 0 or a positive multiple of 1024");
+  if (cfg->block_rows > ((int64_t)1 << 24)) return fail(STATS_E_ARG, "block_rows too large");
+  if (cfg->staging_rows < 0) return fail(STATS_E_ARG, "staging_rows must be >= 0");
+  return STATS_OK;
+}
+
+namespace st {
+
+int open_handle(const stats_config* cfg, int ngroups, stats_ctx** out) {
+  if (!out) return fail(STATS_E_ARG, "out is NULL");
+  *out = nullptr;
+  int rc = validate_cfg(cfg);
+  if (rc) return rc;
+  int ndev = 0;
+  if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
+    return fail(STATS_E_HIP, "no HIP device available");
+  if (cfg->device < 0 || cfg->device >= ndev) return fail(STATS_E_ARG, "device out of range");
+  DeviceGuard g(cfg->device);
+  if (!g.ok) return fail(STATS_E_HIP, "hipSetDevice failed");
+  stats_ctx* h = new (std::nothrow) stats_ctx();
+  if (!h) return fail(STATS_E_NOMEM, "host allocation failed");
+  h->device = cfg->device;
+  h->p = cfg->p;
+  h->cols.assign(cfg->cols, cfg->cols + cfg->p);
+  h->n_planes = cfg->n_planes;
+  for (int k = 0; k < STATS_MAX_PLANES; ++k) h->row_stride[k] = k < cfg->n_planes ? cfg->row_stride[k] : 0;
+  h->precision = cfg->precision;
+  h->staging_rows = cfg->staging_rows ? cfg->staging_rows : ((int64_t)1 << 28);
+  h->block_rows = cfg->block_rows;
+  h->flags = cfg->flags;
+  h->ngroups = ngroups;
+  h->intf.resize(h->p);
+  for (int c = 0; c < h->p; ++c) h->intf[c] = is_int_col(h->cols[c]) ? 1 : 0;
+  if (cfg->stream) {
+    h->stream = (hipStream_t)cfg->stream;
+    h->own_stream = false;
+  } else {
+    hipError_t e = hipStreamCreateWithFlags(&h->stream, hipStreamNonBlocking);
+    if (e != hipSuccess) {
+      delete h;
+      return hip_fail(nullptr, e, "hipStreamCreate");
+    }
+    h->own_stream = true;
+  }
+  const Layout L = Layout::make(h->p);
+  const int64_t nstates = ngroups > 0 ? ngroups : 1;
+  size_t cap;
+  for (int k = 0; k < 2; ++k) {
+    cap = 0;
+    rc = ensure_dev(h, (void**)&h->state[k], &cap, (size_t)(L.words * 8 * nstates));
+    if (rc) {
+      stats_close(h);
+      return rc;
+    }
+  }
+  cap = 0;
+  rc = ensure_dev(h, (void**)&h->intf_dev, &cap, (size_t)h->p);
+  if (!rc) {
+    cap = 0;
+    rc = ensure_dev(h, (void**)&h->status_dev, &cap, sizeof(DevStatus));
+  }
+  if (rc) {
+    stats_close(h);
+    return rc;
+  }
+  hipError_t e = hipMemcpyAsync(h->intf_dev, h->intf.data(), (size_t)h->p, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->state[0], 0, (size_t)(L.words * 8 * nstates), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->status_dev, 0, sizeof(DevStatus), h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    int r = hip_fail(h, e, "initialising handle state");
+    stats_close(h);
+    return r;
+  }
+  h->cur = 0;
+  *out = h;
+  return STATS_OK;
+}
+
+}  // namespace st
+
+extern "C" int stats_open(const stats_config* cfg, stats_ctx** out) {
+  return open_handle(cfg, 0, out);
+}
+
+extern "C" int stats_open_groups(const stats_config* cfg, int32_t ngroups, stats_ctx** out) {
+  if (ngroups < 1 || ngroups > (1 << 24)) {
+    if (out) *out = nullptr;
+    return fail(STATS_E_ARG, "ngroups must be in 1..2^24");
+  }
+  return open_handle(cfg, ngroups, out);
+}
+
+extern "C" void stats_close(stats_ctx* h) {
+  if (!h) return;
+  DeviceGuard g(h->device);
+  if (h->stream) (void)hipStreamSynchronize(h->stream);
+  if (h->copy_stream) (void)hipStreamSynchronize(h->copy_stream);
+  collect_timings(h);
+  void* bufs[] = {h->state[0], h->state[1], h->intf_dev, h->status_dev, h->rec, h->l1,
+                  h->fin_out, h->fin_scratch, h->sel_dev, h->raw_out, h->stage_dev[0],
+                  h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev};
+  for (void* b : bufs)
+    if (b) (void)hipFree(b);
+  for (int k = 0; k < 2; ++k) {
+    if (h->stage_host[k]) (void)hipHostFree(h->stage_host[k]);
+    if (h->ev_copy[k]) (void)hipEventDestroy(h->ev_copy[k]);
+    if (h->ev_free[k]) (void)hipEventDestroy(h->ev_free[k]);
+  }
+  if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
+  if (h->graph) (void)hipGraphDestroy(h->graph);
+  if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
+  if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
+  delete h;
+}
+
+extern "C" const char* stats_last_error(void) { return g_err.c_str(); }
+
+// ---------------------------------------------------------------------------
+// accumulate
+
+namespace st {
+
+// Chooses the kernel layout class for the given plane pointers.
+static int layout_kind(const stats_ctx* h, const void* const* planes) {
+  const int p = h->p;
+  // AoS FP64: one plane, all columns FP64 at consecutive offsets, 16-byte rows.
+  bool aos = true;
+  for (int c = 0; c < p && aos; ++c) {
+    const stats_column& col = h->cols[c];
+    aos = col.dtype == STATS_F64 && col.plane == h->cols[0].plane &&
+          col.byte_offset == h->cols[0].byte_offset + 8 * c;
+  }
+  if (aos) {
+    const int pl = h->cols[0].plane;
+    const uintptr_t base = (uintptr_t)planes[pl] + (uintptr_t)h->cols[0].byte_offset;
+    if (base % 16 == 0 && h->row_stride[pl] % 16 == 0) return 1;
+  }
+  // Dense planes: each column alone in its plane with stride = element size.
+  bool dense = true;
+  std::vector<int> seen(h->n_planes, 0);
+  for (int c = 0; c < p && dense; ++c) {
+    const stats_column& col = h->cols[c];
+    dense = col.byte_offset == 0 && h->row_stride[col.plane] == elem_size(col.dtype) &&
+            !seen[col.plane] && ((uintptr_t)planes[col.plane] % 16 == 0);
+    if (dense) seen[col.plane] = 1;
+  }
+  return dense ? 2 : 0;
+}
+
+static int64_t auto_block_rows(int64_t nrows) {
+  // target ~2048 blocks per launch, between 1024 rows and 2^17 rows per block
+  int64_t R = (nrows + 2047) / 2048;
+  R = ((R + 1023) / 1024) * 1024;
+  return std::max<int64_t>(1024, std::min<int64_t>(R, (int64_t)1 << 17));
+}
+
+// Reduce nrows device-resident rows (plane bases already offset to the first
+// row) into the handle state.  Small p only (p <= 16).
+int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nrows) {
+  const int p = h->p;
+  const int64_t R = h->block_rows ? h->block_rows : auto_block_rows(nrows);
+  AccumLaunch a;
+  memset(&a, 0, sizeof a);
+  a.p = p;
+  a.kind = layout_kind(h, planes);
+  for (int c = 0; c < p; ++c) {
+    const stats_column& col = h->cols[c];
+    a.colbase[c] = (const char*)planes[col.plane] + col.byte_offset;
+    a.colstride[c] = h->row_stride[col.plane];
+    a.dtype[c] = col.dtype;
+    if (h->intf[c]) a.intmask |= 1u << c;
+    if ((col.dtype == STATS_F32 || col.dtype == STATS_F64) && (col.flags & STATS_COL_INTEGER))
+      a.chkmask |= 1u << c;
+  }
+  const int64_t W = rec_words(p);
+  const Layout L = Layout::make(p);
+  const int64_t max_blocks = 16384;
+  int64_t done = 0;
+  while (done < nrows) {
+    const int64_t rows = std::min(nrows - done, max_blocks * R);
+    const int64_t nblocks = (rows + R - 1) / R;
+    int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    if (rc) return rc;
+    const int64_t l1_groups = (nblocks + 31) / 32;
+    rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
+    if (rc) return rc;
+    AccumLaunch b = a;
+    for (int c = 0; c < p; ++c) b.colbase[c] = a.colbase[c] + done * a.colstride[c];
+    b.nrows = rows;
+    b.block_rows = R;
+    b.rec = h->rec;
+    {
+      Timer t;
+      t.begin(h, STATS_K_ACCUM);
+      launch_accum_small_p(b, h->stream);
+      t.end();
+    }
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "accumulate kernel launch");
+    {
+      Timer t;
+      t.begin(h, STATS_K_MERGE);
+      launch_merge_records(h->rec, nblocks, p, a.intmask, h->intf_dev, h->l1, l1_groups,
+                           h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "merge kernel launch");
+    h->cur ^= 1;
+    done += rows;
+  }
+  return STATS_OK;
+}
+
+int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
+  if (h->p <= 16) return accumulate_device_small(h, planes, nrows);
+  return accumulate_device_wide(h, planes, nrows);
+}
+
+// Host input: chunks of staging_rows rows go through two device slots; the
+// copy of chunk k+1 (copy stream) overlaps the reduction of chunk k.
+// Pageable input is first copied into two pinned host slots by the CPU.
+int accumulate_host(stats_ctx* h, const void* const* planes, int64_t nrows, bool pinned) {
+  const int np = h->n_planes;
+  const int64_t S = std::min<int64_t>(h->staging_rows, std::max<int64_t>(nrows, 1));
+  if (!h->copy_stream) {
+    hipError_t e = hipStreamCreateWithFlags(&h->copy_stream, hipStreamNonBlocking);
+    if (e != hipSuccess) return hip_fail(h, e, "hipStreamCreate(copy)");
+    for (int k = 0; k < 2; ++k) {
+      (void)hipEventCreateWithFlags(&h->ev_copy[k], hipEventDisableTiming);
+      (void)hipEventCreateWithFlags(&h->ev_free[k], hipEventDisableTiming);
+      (void)hipEventRecord(h->ev_free[k], h->stream);
+    }
+  }
+  size_t slot_bytes = 0;
+  std::vector<size_t> plane_off(np);
+  for (int k = 0; k < np; ++k) {
+    plane_off[k] = slot_bytes;
+    slot_bytes += (size_t)(((S * h->row_stride[k]) + 255) / 256 * 256);
+  }
+  for (int k = 0; k < 2; ++k) {
+    int rc = ensure_dev(h, &h->stage_dev[k], &h->stage_cap[k], slot_bytes);
+    if (rc) return rc;
+    if (!pinned && h->stage_host_cap[k] < slot_bytes) {
+      if (h->stage_host[k]) {
+        (void)hipEventSynchronize(h->ev_copy[k]);
+        (void)hipHostFree(h->stage_host[k]);
+        h->stage_host[k] = nullptr;
+      }
+      hipError_t e = hipHostMalloc(&h->stage_host[k], slot_bytes, hipHostMallocDefault);
+      if (e != hipSuccess) {
+        h->stage_host[k] = nullptr;
+        h->stage_host_cap[k] = 0;
+        return fail(STATS_E_NOMEM, "hipHostMalloc of the staging slot failed");
+      }
+      h->stage_host_cap[k] = slot_bytes;
+    }
+  }
+  int64_t done = 0;
+  while (done < nrows) {
+    const int k = h->slot;
+    const int64_t rows = std::min(S, nrows - done);
+    // the slot is free once the reduction that last read it has finished
+    hipError_t e = hipStreamWaitEvent(h->copy_stream, h->ev_free[k], 0);
+    const void* dplanes[STATS_MAX_PLANES];
+    for (int q = 0; q < np && e == hipSuccess; ++q) {
+      const char* src = (const char*)planes[q] + done * h->row_stride[q];
+      const size_t bytes = (size_t)(rows * h->row_stride[q]);
+      char* dst = (char*)h->stage_dev[k] + plane_off[q];
+      if (!pinned) {
+        e = hipEventSynchronize(h->ev_copy[k]);  // previous DMA out of the host slot done
+        if (e != hipSuccess) break;
+        char* hs = (char*)h->stage_host[k] + plane_off[q];
+        memcpy(hs, src, bytes);
+        src = hs;
+      }
+      Timer t;
+      t.begin(h, STATS_K_COPY, h->copy_stream);
+      e = hipMemcpyAsync(dst, src, bytes, hipMemcpyHostToDevice, h->copy_stream);
+      t.end();
+      dplanes[q] = dst;
+    }
+    if (e == hipSuccess) e = hipEventRecord(h->ev_copy[k], h->copy_stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(h->stream, h->ev_copy[k], 0);
+    if (e != hipSuccess) return hip_fail(h, e, "staging copy");
+    int rc = accumulate_device(h, dplanes, rows);
+    if (rc) return rc;
+    e = hipEventRecord(h->ev_free[k], h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "hipEventRecord");
+    h->slot ^= 1;
+    done += rows;
+  }
+  if (!pinned) {
+    // pageable input may be reused once we return: wait for the last DMA
+    for (int k = 0; k < 2; ++k) {
+      hipError_t e = hipEventSynchronize(h->ev_copy[k]);
+      if (e != hipSuccess) return hip_fail(h, e, "hipEventSynchronize");
+    }
+  }
+  return STATS_OK;
+}
+
+}  // namespace st
+
+extern "C" int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows,
+                                int32_t mem_kind) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_accumulate_segmented");
+  if (nrows < 0) return fail(STATS_E_ARG, "nrows < 0");
+  if (nrows == 0) return STATS_OK;
+  if (!planes) return fail(STATS_E_ARG, "planes is NULL");
+  for (int k = 0; k < h->n_planes; ++k) {
+    bool used = false;
+    for (const auto& c : h->cols) used |= c.plane == k;
+    if (used && !planes[k]) return fail(STATS_E_ARG, "plane " + std::to_string(k) + " is NULL");
+  }
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(STATS_E_HIP, "hipSetDevice failed");
+  switch (mem_kind) {
+    case STATS_MEM_DEVICE: {
+      for (int k = 0; k < h->n_planes; ++k)
+        if (planes[k] && ((uintptr_t)planes[k] % 16) != 0)
+          return fail(STATS_E_ARG, "device planes must be 16-byte aligned");
+      return accumulate_device(h, planes, nrows);
+    }
+    case STATS_MEM_HOST_PINNED: return accumulate_host(h, planes, nrows, true);
+    case STATS_MEM_HOST: return accumulate_host(h, planes, nrows, false);
+    default: return fail(STATS_E_ARG, "unknown mem_kind");
+  }
+}
+
+extern "C" int stats_sync(stats_ctx* h) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  DeviceGuard g(h->device);
+  return sync_handle(h);
+}
+
+// ---------------------------------------------------------------------------
+// merge
+
+extern "C" int stats_merge(stats_ctx* dst, const stats_ctx* src) {
+  if (!dst || !src) return fail(STATS_E_ARG, "handle is NULL");
+  if (dst == src) return fail(STATS_E_ARG, "dst and src are the same handle");
+  if (dst->poisoned || src->poisoned) return fail(STATS_E_STATE, "handle is poisoned");
+  if (dst->ngroups || src->ngroups) return fail(STATS_E_STATE, "merge of groups handles");
+  if (dst->p != src->p) return fail(STATS_E_MISMATCH, "different column counts");
+  for (int c = 0; c < dst->p; ++c)
+    if (dst->intf[c] != src->intf[c]) return fail(STATS_E_MISMATCH, "different column kinds");
+  stats_ctx* s = const_cast<stats_ctx*>(src);
+  DeviceGuard g(dst->device);
+  const Layout L = Layout::make(dst->p);
+  const size_t bytes = (size_t)L.words * 8;
+  const uint64_t* src_state = s->state[s->cur];
+  hipError_t e;
+  if (s->device != dst->device) {
+    // bring the source state over through the host
+    std::vector<uint64_t> tmp(L.words);
+    {
+      DeviceGuard gs(s->device);
+      e = hipStreamSynchronize(s->stream);
+      if (e == hipSuccess) e = hipMemcpy(tmp.data(), src_state, bytes, hipMemcpyDeviceToHost);
+      if (e != hipSuccess) return hip_fail(s, e, "reading source state");
+    }
+    int rc = ensure_dev(dst, &dst->aux_dev, &dst->aux_cap, bytes);
+    if (rc) return rc;
+    e = hipMemcpyAsync(dst->aux_dev, tmp.data(), bytes, hipMemcpyHostToDevice, dst->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(dst->stream);
+    if (e != hipSuccess) return hip_fail(dst, e, "uploading source state");
+    src_state = (const uint64_t*)dst->aux_dev;
+  } else if (s->stream != dst->stream) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, s->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(dst->stream, ev, 0);
+    if (e == hipSuccess) e = hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(dst, e, "ordering src before dst");
+  }
+  launch_merge_states(dst->state[dst->cur], src_state, dst->state[dst->cur ^ 1], dst->p,
+                      dst->intf_dev, dst->stream);
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(dst, e, "merge kernel launch");
+  dst->cur ^= 1;
+  // the source must not change under the pending merge: later writes to src
+  // are ordered on src's stream, so make src wait for dst
+  if (s->device == dst->device && s->stream != dst->stream) {
+    hipEvent_t ev;
+    e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+    if (e == hipSuccess) e = hipEventRecord(ev, dst->stream);
+    if (e == hipSuccess) e = hipStreamWaitEvent(s->stream, ev, 0);
+    if (e == hipSuccess) e = hipEventDestroy(ev);
+    if (e != hipSuccess) return hip_fail(dst, e, "ordering dst before src");
+  }
+  return STATS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// raw statistics and finalize
+
+namespace st {
+
+int raw_of_state(stats_ctx* h, const uint64_t* state_dev, int64_t* n, stats_i128* s_int,
+                 double* s_f64, stats_i128* C_int, double* C_f64, uint8_t* exact_mask) {
+  const int p = h->p;
+  const Layout L = Layout::make(p);
+  int rc = ensure_dev(h, (void**)&h->raw_out, &h->raw_cap, (size_t)(p + (int64_t)p * p) * 8);
+  if (rc) return rc;
+  launch_raw(state_dev, p, h->intf_dev, h->raw_out, h->stream);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "raw kernel launch");
+  std::vector<uint64_t> st(L.words);
+  std::vector<double> raw(p + (size_t)p * p);
+  e = hipMemcpyAsync(st.data(), state_dev, (size_t)L.words * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(raw.data(), h->raw_out, raw.size() * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "reading statistics");
+  if (n) *n = (int64_t)st[0];
+  for (int i = 0; i < p; ++i) {
+    if (s_int) {
+      if (h->intf[i]) {
+        s_int[i].lo = st[L.off_s + 2 * i];
+        s_int[i].hi = (int64_t)st[L.off_s + 2 * i + 1];
+      } else {
+        s_int[i].lo = 0;
+        s_int[i].hi = 0;
+      }
+    }
+    if (s_f64) s_f64[i] = raw[i];
+    for (int j = 0; j < p; ++j) {
+      const int a = std::min(i, j), b = std::max(i, j);
+      const bool ex = h->intf[a] && h->intf[b];
+      const int64_t t = tri(p, a, b);
+      if (C_int) {
+        C_int[(int64_t)i * p + j].lo = ex ? st[L.off_C + 2 * t] : 0;
+        C_int[(int64_t)i * p + j].hi = ex ? (int64_t)st[L.off_C + 2 * t + 1] : 0;
+      }
+      if (C_f64) C_f64[(int64_t)i * p + j] = raw[p + (int64_t)i * p + j];
+      if (exact_mask) exact_mask[(int64_t)i * p + j] = ex ? 1 : 0;
+    }
+  }
+  return STATS_OK;
+}
+
+int selection(const stats_ctx* h, const stats_finalize_opts* o, std::vector<int32_t>* sel) {
+  sel->clear();
+  bool any = false;
+  for (int w = 0; w < STATS_MASK_WORDS; ++w) any |= o->column_mask[w] != 0;
+  for (int c = 0; c < h->p; ++c) {
+    const bool keep = any ? ((o->column_mask[c / 64] >> (c % 64)) & 1u)
+                          : !(h->cols[c].flags & STATS_COL_IDENTIFIER);
+    if (keep) sel->push_back(c);
+  }
+  if (any) {
+    for (int c = h->p; c < STATS_MAX_P; ++c)
+      if ((o->column_mask[c / 64] >> (c % 64)) & 1u)
+        return fail(STATS_E_ARG, "column_mask selects a column >= p");
+  }
+  if (sel->empty()) return fail(STATS_E_ARG, "no column selected");
+  if (o->ddof < 0) return fail(STATS_E_ARG, "ddof < 0");
+  if (o->pca_on != 0 && o->pca_on != 1) return fail(STATS_E_ARG, "pca_on must be 0 or 1");
+  return STATS_OK;
+}
+
+}  // namespace st
+
+extern "C" int stats_raw(stats_ctx* h, int64_t* n, stats_i128* s_int, double* s_f64,
+                         stats_i128* C_int, double* C_f64, uint8_t* exact_mask) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_group_raw");
+  DeviceGuard g(h->device);
+  int rc = sync_handle(h);
+  if (rc) return rc;
+  return raw_of_state(h, h->state[h->cur], n, s_int, s_f64, C_int, C_f64, exact_mask);
+}
+
+extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int32_t* p_out,
+                              double* mean, double* cov, double* corr, double* eigval,
+                              double* eigvec, double* var_pct, double* cum_pct) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_finalize_groups");
+  stats_finalize_opts def;
+  memset(&def, 0, sizeof def);
+  def.ddof = 1;
+  def.want_vectors = 1;
+  const stats_finalize_opts* o = opts ? opts : &def;
+  std::vector<int32_t> sel;
+  int rc = selection(h, o, &sel);
+  if (rc) return rc;
+  DeviceGuard g(h->device);
+  rc = sync_handle(h);
+  if (rc) return rc;
+  int64_t n = 0;
+  hipError_t e = hipMemcpy(&n, h->state[h->cur], 8, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "reading n");
+  if (n <= o->ddof) return fail(STATS_E_STATE, "N <= ddof: covariance undefined");
+  const int q = (int)sel.size();
+  const size_t out_words = (size_t)q * 4 + 3 * (size_t)q * q;
+  rc = ensure_dev(h, (void**)&h->fin_out, &h->fin_out_cap, out_words * 8);
+  if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, 2 * (size_t)q * q * 8);
+  if (!rc) rc = ensure_dev(h, (void**)&h->sel_dev, &h->sel_cap, (size_t)q * 4);
+  if (rc) return rc;
+  e = hipMemcpyAsync(h->sel_dev, sel.data(), (size_t)q * 4, hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "uploading selection");
+  FinalizeLaunch F;
+  F.state = h->state[h->cur];
+  F.p = h->p;
+  F.sel_dev = h->sel_dev;
+  F.q = q;
+  F.intflags_dev = h->intf_dev;
+  F.ddof = o->ddof;
+  F.pca_on = o->pca_on;
+  F.want_vectors = 1;
+  F.out = h->fin_out;
+  F.scratch = h->fin_scratch;
+  {
+    Timer t;
+    t.begin(h, STATS_K_FINALIZE);
+    launch_finalize(F, h->stream);
+    t.end();
+  }
+  e = hipGetLastError();
+  if (e != hipSuccess) return hip_fail(h, e, "finalize kernel launch");
+  std::vector<double> out(out_words);
+  e = hipMemcpyAsync(out.data(), h->fin_out, out_words * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "finalize");
+  collect_timings(h);
+  const size_t qq = (size_t)q * q;
+  const double* po = out.data();
+  if (p_out) *p_out = q;
+  if (mean) memcpy(mean, po, q * 8);
+  if (cov) memcpy(cov, po + q, qq * 8);
+  if (corr) memcpy(corr, po + q + qq, qq * 8);
+  if (eigval) memcpy(eigval, po + q + 2 * qq, q * 8);
+  if (eigvec) memcpy(eigvec, po + 2 * q + 2 * qq, qq * 8);
+  if (var_pct) memcpy(var_pct, po + 2 * q + 3 * qq, q * 8);
+  if (cum_pct) memcpy(cum_pct, po + 3 * q + 3 * qq, q * 8);
+  return STATS_OK;
+}
+
+// ---------------------------------------------------------------------------
+// checkpoint
+
+static const char kMagic[8] = {'S', 'T', 'S', 'T', 'A', 'T', 'S', '1'};
+
+extern "C" int stats_serialize(stats_ctx* h, void* buf, size_t* len) {
+  if (!h || !len) return fail(STATS_E_ARG, "NULL argument");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handles are not serialized");
+  const Layout L = Layout::make(h->p);
+  const size_t need = 8 + 8 + (size_t)h->p * 8 + (size_t)L.words * 8;
+  if (!buf) {
+    *len = need;
+    return STATS_OK;
+  }
+  if (*len < need) return fail(STATS_E_ARG, "buffer too small");
+  DeviceGuard g(h->device);
+  int rc = sync_handle(h);
+  if (rc) return rc;
+  char* o = (char*)buf;
+  memcpy(o, kMagic, 8);
+  const int64_t p = h->p;
+  memcpy(o + 8, &p, 8);
+  for (int c = 0; c < h->p; ++c) {
+    const int32_t sig[2] = {h->cols[c].dtype, (int32_t)(h->intf[c] | (h->cols[c].flags << 1))};
+    memcpy(o + 16 + 8 * c, sig, 8);
+  }
+  hipError_t e = hipMemcpy(o + 16 + 8 * (size_t)h->p, h->state[h->cur], (size_t)L.words * 8,
+                           hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "reading state");
+  *len = need;
+  return STATS_OK;
+}
+
+extern "C" int stats_deserialize(const void* buf, size_t len, const stats_config* cfg,
+                                 stats_ctx** out) {
+  if (out) *out = nullptr;
+  if (!buf || !cfg || !out) return fail(STATS_E_ARG, "NULL argument");
+  if (len < 16 || memcmp(buf, kMagic, 8) != 0) return fail(STATS_E_ARG, "not a statistics checkpoint");
+  int64_t p;
+  memcpy(&p, (const char*)buf + 8, 8);
+  if (p != cfg->p) return fail(STATS_E_MISMATCH, "checkpoint has a different column count");
+  const Layout L = Layout::make((int)p);
+  if (len != 16 + 8 * (size_t)p + (size_t)L.words * 8) return fail(STATS_E_ARG, "checkpoint size mismatch");
+  stats_ctx* h = nullptr;
+  int rc = stats_open(cfg, &h);
+  if (rc) return rc;
+  for (int c = 0; c < h->p; ++c) {
+    int32_t sig[2];
+    memcpy(sig, (const char*)buf + 16 + 8 * c, 8);
+    if (sig[0] != h->cols[c].dtype || sig[1] != (int32_t)(h->intf[c] | (h->cols[c].flags << 1))) {
+      stats_close(h);
+      return fail(STATS_E_MISMATCH, "checkpoint column " + std::to_string(c) + " differs");
+    }
+  }
+  DeviceGuard g(h->device);
+  hipError_t e = hipMemcpyAsync(h->state[h->cur], (const char*)buf + 16 + 8 * p, (size_t)L.words * 8,
+                                hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) {
+    rc = hip_fail(h, e, "uploading checkpoint");
+    stats_close(h);
+    return rc;
+  }
+  *out = h;
+  return STATS_OK;
+}
+
+extern "C" int stats_kernel_time(stats_ctx* h, int32_t which, int64_t* launches, double* total_ms) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (which < 0 || which >= STATS_K_COUNT) return fail(STATS_E_ARG, "unknown kernel id");
+  if (!(h->flags & STATS_CFG_TIMING)) return fail(STATS_E_STATE, "handle opened without STATS_CFG_TIMING");
+  if (launches) *launches = h->kt_n[which];
+  if (total_ms) *total_ms = h->kt_ms[which];
+  return STATS_OK;
+}

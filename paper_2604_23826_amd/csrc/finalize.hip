@@ -1,0 +1,322 @@
+// Means, covariance, correlation and PCA from the statistics alone.
+//
+// Section "Data Representation and Sufficient Statistics": once (N, s, X^T X)
+// are known, means, covariance and correlation follow without the rows.
+// Section "Numerical Considerations": the identifier column is excluded
+// (column selection) and the covariance is never formed as X^T X - N mu mu^T
+// in floating point: integer pairs use the exact numerator
+// N C_ij - s_i s_j (256-bit) divided once with correct rounding, other pairs
+// the merged centred co-moment M2 / (N - ddof).
+// Section "Principal Component Analysis Results": eigenpairs of the (small,
+// dense) correlation or covariance matrix; here a cyclic Jacobi method in
+// FP64 with the round-robin (Brent-Luk) ordering, so that in every round
+// q/2 disjoint rotations are computed and applied in parallel.  Output as in
+// Table 3: eigenvalues descending, variance %, cumulative %, loadings (one
+// row per component).
+//
+// One workgroup does the whole job; the matrices live in a global scratch
+// buffer (they stay in L2).
+#include "common.hpp"
+
+namespace st {
+namespace {
+
+constexpr int kThreads = 1024;
+
+struct Args {
+  const uint64_t* state;
+  int p;
+  const int32_t* sel;
+  int q;
+  const uint8_t* intf;
+  int ddof;
+  int pca_on;
+  int want_vectors;
+  double* out;
+  double* scratch;
+};
+
+__device__ inline double exact_cov(const uint64_t* st, const Layout& L, int i, int j, int64_t n,
+                                   int ddof) {
+  const i128 si = load_i128(st + L.off_s + 2 * i);
+  const i128 sj = load_i128(st + L.off_s + 2 * j);
+  const i128 cij = load_i128(st + L.off_C + 2 * tri(L.p, i, j));
+  bool neg;
+  U256 num = i256_mul_sub((i128)n, cij, si, sj, &neg);  // n C_ij - s_i s_j
+  const U256 den = u256_mul128((u128)n, (u128)(n - ddof));
+  return u256_div_to_double(neg, num, den);
+}
+
+__device__ inline double exact_mean(const uint64_t* st, const Layout& L, int i, int64_t n) {
+  bool neg;
+  const u128 m = abs128(load_i128(st + L.off_s + 2 * i), &neg);
+  return u256_div_to_double(neg, u256_from_u128(m), u256_from_u128((u128)n));
+}
+
+// Round-robin schedule on m (even) players: player at position pos in round r.
+__device__ inline int rr_player(int pos, int r, int m) {
+  return pos == 0 ? 0 : ((pos - 1 + r) % (m - 1)) + 1;
+}
+
+__global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
+  const Layout L = Layout::make(f.p);
+  const uint64_t* st = f.state;
+  const int64_t n = (int64_t)st[0];
+  const int q = f.q;
+  const int tid = threadIdx.x;
+  double* mean = f.out;
+  double* cov = mean + q;
+  double* corr = cov + (int64_t)q * q;
+  double* ev = corr + (int64_t)q * q;
+  double* evec = ev + q;
+  double* varp = evec + (int64_t)q * q;
+  double* cump = varp + q;
+  double* A = f.scratch;
+  double* V = A + (int64_t)q * q;
+
+  __shared__ int s_flag;
+  __shared__ int s_rot;
+  const int m = q + (q & 1);  // players (a dummy when q is odd)
+  const int npairs = m / 2;
+  extern __shared__ double s_dyn[];  // c[npairs], s[npairs], t[npairs], apq[npairs], pair p/q
+  double* rc = s_dyn;
+  double* rs = rc + npairs;
+  double* rt = rs + npairs;
+  double* rapq = rt + npairs;
+  int* pp = (int*)(rapq + npairs);
+  int* pq = pp + npairs;
+
+  // ---- means and covariance ----
+  const double dn = (double)(n - f.ddof);
+  for (int a = tid; a < q; a += kThreads) {
+    const int i = f.sel[a];
+    mean[a] = f.intf[i] ? exact_mean(st, L, i, n)
+                        : __longlong_as_double((long long)st[L.off_mu + i]);
+  }
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+    const int a = (int)(idx / q), b = (int)(idx % q);
+    if (a > b) continue;
+    const int i = f.sel[a], j = f.sel[b];  // sel ascending, so i <= j
+    double v;
+    if (f.intf[i] && f.intf[j]) v = exact_cov(st, L, i, j, n, f.ddof);
+    else v = __longlong_as_double((long long)st[L.off_M2 + tri(L.p, i, j)]) / dn;
+    cov[(int64_t)a * q + b] = v;
+    cov[(int64_t)b * q + a] = v;
+  }
+  __syncthreads();
+  // ---- correlation ----
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+    const int a = (int)(idx / q), b = (int)(idx % q);
+    const double caa = cov[(int64_t)a * q + a], cbb = cov[(int64_t)b * q + b];
+    double v;
+    if (caa == 0.0 || cbb == 0.0) v = __builtin_nan("");
+    else if (a == b) v = 1.0;
+    else v = cov[idx] / sqrt(caa * cbb);
+    corr[idx] = v;
+  }
+  if (tid == 0) s_flag = 0;
+  __syncthreads();
+  // ---- PCA input ----
+  const double* M = f.pca_on ? cov : corr;
+  int bad = 0;
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+    const double v = M[idx];
+    if (!isfinite(v)) bad = 1;
+    A[idx] = v;
+    V[idx] = (idx / q == idx % q) ? 1.0 : 0.0;
+  }
+  if (bad) atomicOr(&s_flag, 1);
+  __syncthreads();
+  if (s_flag) {
+    for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) evec[idx] = __builtin_nan("");
+    for (int a = tid; a < q; a += kThreads) {
+      ev[a] = varp[a] = cump[a] = __builtin_nan("");
+    }
+    return;
+  }
+
+  // ---- cyclic Jacobi, round-robin ordering ----
+  const double tol = 2.220446049250313e-16;
+  for (int sweep = 0; sweep < 60 && q > 1; ++sweep) {
+    if (tid == 0) s_rot = 0;
+    __syncthreads();
+    for (int r = 0; r < m - 1; ++r) {
+      // rotations of this round (one thread per disjoint pair)
+      for (int k = tid; k < npairs; k += kThreads) {
+        int a = rr_player(k, r, m), b = rr_player(m - 1 - k, r, m);
+        if (a > b) {
+          const int x = a;
+          a = b;
+          b = x;
+        }
+        pp[k] = a;
+        pq[k] = b;
+        double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
+        if (b < q) {
+          apq = A[(int64_t)a * q + b];
+          const double app = A[(int64_t)a * q + a], aqq = A[(int64_t)b * q + b];
+          if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+            const double theta = (aqq - app) / (2.0 * apq);
+            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+            c = 1.0 / sqrt(t * t + 1.0);
+            s = t * c;
+            atomicAdd(&s_rot, 1);
+          } else {
+            apq = 0.0;
+          }
+        }
+        rc[k] = c;
+        rs[k] = s;
+        rt[k] = t;
+        rapq[k] = apq;
+      }
+      __syncthreads();
+      // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns)
+      for (int64_t idx = tid; idx < (int64_t)npairs * npairs; idx += kThreads) {
+        const int u = (int)(idx / npairs), v = (int)(idx % npairs);
+        const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
+        const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
+        if (su == 0.0 && sv == 0.0) continue;
+        const bool bq = b < q, dq = d2 < q;
+        double x00 = A[(int64_t)a * q + c2];
+        double x01 = dq ? A[(int64_t)a * q + d2] : 0.0;
+        double x10 = bq ? A[(int64_t)b * q + c2] : 0.0;
+        double x11 = (bq && dq) ? A[(int64_t)b * q + d2] : 0.0;
+        // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
+        const double y00 = cu * x00 - su * x10, y10 = su * x00 + cu * x10;
+        const double y01 = cu * x01 - su * x11, y11 = su * x01 + cu * x11;
+        // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
+        double z00 = cv * y00 - sv * y01, z01 = sv * y00 + cv * y01;
+        double z10 = cv * y10 - sv * y11, z11 = sv * y10 + cv * y11;
+        if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
+          const double t = rt[u], apq = rapq[u];
+          z00 = A[(int64_t)a * q + a] - t * apq;
+          z11 = A[(int64_t)b * q + b] + t * apq;
+          z01 = 0.0;
+          z10 = 0.0;
+        }
+        A[(int64_t)a * q + c2] = z00;
+        if (dq) A[(int64_t)a * q + d2] = z01;
+        if (bq) A[(int64_t)b * q + c2] = z10;
+        if (bq && dq) A[(int64_t)b * q + d2] = z11;
+      }
+      // V <- V J
+      for (int64_t idx = tid; idx < (int64_t)q * npairs; idx += kThreads) {
+        const int row = (int)(idx / npairs), u = (int)(idx % npairs);
+        const double s = rs[u];
+        if (s == 0.0) continue;
+        const int a = pp[u], b = pq[u];
+        const double c = rc[u];
+        const double va = V[(int64_t)row * q + a], vb = V[(int64_t)row * q + b];
+        V[(int64_t)row * q + a] = c * va - s * vb;
+        V[(int64_t)row * q + b] = s * va + c * vb;
+      }
+      __syncthreads();
+    }
+    if (s_rot == 0) break;
+    __syncthreads();
+  }
+
+  // ---- sort descending (ties: lower index first), sign rule, percentages ----
+  for (int k = tid; k < q; k += kThreads) {
+    const double lk = A[(int64_t)k * q + k];
+    int rank = 0;
+    for (int j = 0; j < q; ++j) {
+      const double lj = A[(int64_t)j * q + j];
+      rank += (lj > lk) || (lj == lk && j < k);
+    }
+    ev[rank] = lk;
+    // eigenvector k = column k of V; sign: largest |entry| positive (lowest index on ties)
+    int arg = 0;
+    double best = -1.0;
+    for (int j = 0; j < q; ++j) {
+      const double a = fabs(V[(int64_t)j * q + k]);
+      if (a > best) {
+        best = a;
+        arg = j;
+      }
+    }
+    const double sg = V[(int64_t)arg * q + k] < 0.0 ? -1.0 : 1.0;
+    if (f.want_vectors)
+      for (int j = 0; j < q; ++j) evec[(int64_t)rank * q + j] = sg * V[(int64_t)j * q + k];
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double tot = 0.0;
+    for (int k = 0; k < q; ++k) tot += ev[k];
+    double run = 0.0;
+    for (int k = 0; k < q; ++k) {
+      varp[k] = 100.0 * ev[k] / tot;
+      run += varp[k];
+      cump[k] = run;
+    }
+  }
+}
+
+__global__ void k_raw(const uint64_t* st, int p, const uint8_t* intf, double* out) {
+  // out: s_f64[p], C_f64[p*p]
+  const Layout L = Layout::make(p);
+  const int64_t n = (int64_t)st[0];
+  const double dn = (double)n;
+  for (int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; idx < p + (int64_t)p * p;
+       idx += (int64_t)gridDim.x * blockDim.x) {
+    if (idx < p) {
+      const int i = (int)idx;
+      double v;
+      if (intf[i]) {
+        bool neg;
+        const u128 m = abs128(load_i128(st + L.off_s + 2 * i), &neg);
+        v = u256_div_to_double(neg, u256_from_u128(m), u256_from_u128(1));
+      } else {
+        v = dn * __longlong_as_double((long long)st[L.off_mu + i]);
+      }
+      out[i] = v;
+    } else {
+      const int64_t e = idx - p;
+      int i = (int)(e / p), j = (int)(e % p);
+      if (i > j) {
+        const int x = i;
+        i = j;
+        j = x;
+      }
+      double v;
+      if (intf[i] && intf[j]) {
+        bool neg;
+        const u128 m = abs128(load_i128(st + L.off_C + 2 * tri(p, i, j)), &neg);
+        v = u256_div_to_double(neg, u256_from_u128(m), u256_from_u128(1));
+      } else {
+        const double mi = __longlong_as_double((long long)st[L.off_mu + i]);
+        const double mj = __longlong_as_double((long long)st[L.off_mu + j]);
+        v = __longlong_as_double((long long)st[L.off_M2 + tri(p, i, j)]) + dn * mi * mj;
+      }
+      out[idx] = v;
+    }
+  }
+}
+
+}  // namespace
+
+void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
+  Args a;
+  a.state = F.state;
+  a.p = F.p;
+  a.sel = F.sel_dev;
+  a.q = F.q;
+  a.intf = F.intflags_dev;
+  a.ddof = F.ddof;
+  a.pca_on = F.pca_on;
+  a.want_vectors = F.want_vectors;
+  a.out = F.out;
+  a.scratch = F.scratch;
+  const int npairs = (F.q + (F.q & 1)) / 2;
+  const size_t shm = (size_t)npairs * (4 * sizeof(double) + 2 * sizeof(int));
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), shm, s, a);
+}
+
+void launch_raw(const uint64_t* state, int p, const uint8_t* intf, double* out, hipStream_t s) {
+  const int64_t work = p + (int64_t)p * p;
+  const unsigned blocks = (unsigned)std::min<int64_t>((work + 255) / 256, 1024);
+  hipLaunchKernelGGL(k_raw, dim3(blocks), dim3(256), 0, s, state, p, intf, out);
+}
+
+}  // namespace st

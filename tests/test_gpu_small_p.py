@@ -1,0 +1,278 @@
+"""GPU parity of the narrow-table path (p <= 16) against the CPU oracle, through
+the C ABI.  Integer columns: bit-exact sums, cross products and covariances;
+floating columns: correlation-scaled covariance error <= 1e-12."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from helpers import (TABLE1_INT, aos_config, check_final_against_oracle, check_raw_against_oracle,
+                     current_stream, lib, planar_config, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+SEL = list(range(1, 10))  # identifier excluded
+
+
+def _oracle(x, is_int=TABLE1_INT, mask=SEL):
+    st = oracle.sufficient_stats(oracle.columns_of(x), is_int)
+    return st, (oracle.finalize(st, mask=mask) if st.n > 1 else None)
+
+
+def _run_aos(x, **kw):
+    L = lib()
+    cfg = aos_config(stream=current_stream(), **kw)
+    h = L.stats_open(cfg)
+    try:
+        d = to_dev(x)
+        L.stats_accumulate(h, [d], x.shape[0])
+        raw = L.stats_raw(h, 10)
+        fin = L.stats_finalize(h, 10) if x.shape[0] > 1 else None
+    finally:
+        L.stats_close(h)
+    return raw, fin
+
+
+@pytest.mark.parametrize("n", [1, 2, 3, 1023, 1024, 1025, 4097, 100_003])
+def test_aos_fp64_table1(n):
+    print(f"aos n={n}", flush=True)
+    x = datagen.table1_aos(1, n)
+    raw, fin = _run_aos(x)
+    st, ref = _oracle(x)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+    if n > 1:
+        check_final_against_oracle(fin, ref, [TABLE1_INT[c] for c in SEL])
+
+
+@pytest.mark.parametrize("n", [1, 5, 2047, 2048, 2049, 300_001])
+def test_planar_int32_fp64(n):
+    print(f"planar n={n}", flush=True)
+    L = lib()
+    planes = datagen.table1_planar(2, n)
+    dplanes = [to_dev(p) for p in planes]
+    h = L.stats_open(planar_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, dplanes, n)
+        raw = L.stats_raw(h, 10)
+        fin = L.stats_finalize(h, 10) if n > 1 else None
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(planes, TABLE1_INT)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+    if n > 1:
+        check_final_against_oracle(fin, oracle.finalize(st, mask=SEL), [TABLE1_INT[c] for c in SEL])
+
+
+@pytest.mark.parametrize("block_rows", [1024, 4096, 131072])
+def test_block_size_does_not_change_integers(block_rows):
+    x = datagen.table1_aos(3, 200_000)
+    raw, fin = _run_aos(x, block_rows=block_rows)
+    st, ref = _oracle(x)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+    check_final_against_oracle(fin, ref, [TABLE1_INT[c] for c in SEL])
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 7, 16])
+def test_generic_layout_mixed_dtypes(p):
+    # strided, interleaved columns of several storage types in two planes
+    L = lib()
+    rng = np.random.default_rng(p)
+    n = 50_001
+    dtypes = [np.int32, np.float64, np.int64, np.float32][:4] * 4
+    dtypes = dtypes[:p]
+    arrs = []
+    for c, dt in enumerate(dtypes):
+        if np.issubdtype(dt, np.integer):
+            arrs.append(rng.integers(-50_000, 50_000, size=n).astype(dt))
+        else:
+            arrs.append((rng.normal(100.0 * (c + 1), 3.0 + c, size=n)).astype(dt))
+    # plane 0: a packed record of all columns with padding; plane 1 unused
+    rec_dt = np.dtype({"names": [f"c{c}" for c in range(p)], "formats": dtypes,
+                       "offsets": [16 * c for c in range(p)], "itemsize": 16 * p + 8})
+    rec = np.zeros(n, dtype=rec_dt)
+    for c in range(p):
+        rec[f"c{c}"] = arrs[c]
+    raw_bytes = rec.view(np.uint8).reshape(n, rec_dt.itemsize)
+    cols = [(L.DTYPE_CODE[np.dtype(dt)], 0, 16 * c, 0) for c, dt in enumerate(dtypes)]
+    cfg = L.make_config(cols, [rec_dt.itemsize, 8], stream=current_stream())
+    h = L.stats_open(cfg)
+    d = to_dev(raw_bytes)
+    try:
+        L.stats_accumulate(h, [d, d], n)
+        raw = L.stats_raw(h, p)
+        fin = L.stats_finalize(h, p)
+    finally:
+        L.stats_close(h)
+    is_int = [np.issubdtype(dt, np.integer) for dt in dtypes]
+    st = oracle.sufficient_stats(arrs, is_int)
+    check_raw_against_oracle(raw, st, is_int)
+    check_final_against_oracle(fin, oracle.finalize(st), is_int)
+
+
+def test_identifier_closed_forms_full_c1():
+    # 10^6 Table-1 rows (the small configuration): identifier sums by closed form
+    n = 1_000_000
+    x = datagen.table1_aos(1, n)
+    raw, fin = _run_aos(x)
+    assert raw["s_int"][0] == n * (n + 1) // 2 == 500_000_500_000
+    assert raw["C_int"][0][0] == n * (n + 1) * (2 * n + 1) // 6 == 333_333_833_333_500_000
+    st, ref = _oracle(x)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+    check_final_against_oracle(fin, ref, [TABLE1_INT[c] for c in SEL])
+
+
+def test_include_identifier_is_exact():
+    # the identifier kept: var(A) = N(N+1)/12 exactly (no negative variance)
+    from fractions import Fraction
+    L = lib()
+    n = 4_000_000
+    x = datagen.table1_aos(5, n)
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], n)
+        fin = L.stats_finalize(h, 10, mask=list(range(10)))
+    finally:
+        L.stats_close(h)
+    assert fin["cov"][0, 0] == float(Fraction(n * (n + 1), 12))
+    assert np.all(np.isfinite(fin["corr"]))
+
+
+def test_chunks_and_merge_equal_single_pass():
+    L = lib()
+    n = 250_000
+    x = datagen.table1_aos(6, n)
+    d = to_dev(x)
+    s = current_stream()
+    h1 = L.stats_open(aos_config(stream=s))
+    h2 = L.stats_open(aos_config(stream=s))
+    h3 = L.stats_open(aos_config(stream=s))
+    try:
+        L.stats_accumulate(h1, [d], n)
+        cuts = [0, 1, 77_777, 77_778, 200_000, n]
+        for a, b in zip(cuts[:-1], cuts[1:]):
+            L.stats_accumulate(h2 if a < 100_000 else h3, [d[a:]], b - a)
+        L.stats_merge(h2, h3)
+        r1, r2 = L.stats_raw(h1, 10), L.stats_raw(h2, 10)
+        f1, f2 = L.stats_finalize(h1, 10), L.stats_finalize(h2, 10)
+    finally:
+        for h in (h1, h2, h3):
+            L.stats_close(h)
+    assert r1["n"] == r2["n"] == n
+    assert r1["s_int"] == r2["s_int"] and r1["C_int"] == r2["C_int"]
+    from helpers import corr_scaled_err
+    assert corr_scaled_err(f2["cov"], f1["cov"]) <= 1e-14
+
+
+def test_repeated_runs_bitwise_identical():
+    x = datagen.table1_aos(7, 123_457)
+    a = _run_aos(x)
+    b = _run_aos(x)
+    for k in ("cov", "corr", "eigval", "eigvec", "mean"):
+        assert np.array_equal(a[1][k].view(np.uint64), b[1][k].view(np.uint64)), k
+
+
+def test_host_staging_pinned_and_pageable():
+    import torch
+    L = lib()
+    n = 100_000
+    planes = datagen.table1_planar(8, n)
+    st = oracle.sufficient_stats(planes, TABLE1_INT)
+    ref = oracle.finalize(st, mask=SEL)
+    for kind in (L.STATS_MEM_HOST_PINNED, L.STATS_MEM_HOST):
+        if kind == L.STATS_MEM_HOST_PINNED:
+            src = [torch.from_numpy(p).pin_memory() for p in planes]
+        else:
+            src = planes
+        h = L.stats_open(planar_config(stream=current_stream(), staging_rows=30_000))
+        try:
+            L.stats_accumulate(h, src, n, kind)
+            raw = L.stats_raw(h, 10)
+            fin = L.stats_finalize(h, 10)
+        finally:
+            L.stats_close(h)
+        check_raw_against_oracle(raw, st, TABLE1_INT)
+        check_final_against_oracle(fin, ref, [TABLE1_INT[c] for c in SEL])
+
+
+def test_inexact_integer_column_is_reported():
+    L = lib()
+    x = datagen.table1_aos(9, 5000)
+    x[1234, 3] += 0.5  # D declared integer but holds a fraction
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], 5000)
+        with pytest.raises(L.StatsError) as e:
+            L.stats_sync(h)
+        assert e.value.code == L.STATS_E_INEXACT
+    finally:
+        L.stats_close(h)
+    y = datagen.table1_aos(9, 5000)
+    y[:, 5] += 2.0 ** 41  # beyond the exact range of the shift
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(y)], 5000)
+        with pytest.raises(L.StatsError) as e:
+            L.stats_raw(h, 10)
+        assert e.value.code == L.STATS_E_INEXACT
+    finally:
+        L.stats_close(h)
+
+
+def test_serialize_resume_equals_uninterrupted():
+    L = lib()
+    n = 60_000
+    x = datagen.table1_aos(10, n)
+    d = to_dev(x)
+    s = current_stream()
+    h = L.stats_open(aos_config(stream=s))
+    L.stats_accumulate(h, [d], 25_000)
+    blob = L.stats_serialize(h)
+    L.stats_close(h)
+    h2 = L.stats_deserialize(blob, aos_config(stream=s))
+    L.stats_accumulate(h2, [d[25_000:]], n - 25_000)
+    r2 = L.stats_raw(h2, 10)
+    L.stats_close(h2)
+    st, _ = _oracle(x)
+    check_raw_against_oracle(r2, st, TABLE1_INT)
+    with pytest.raises(L.StatsError) as e:
+        L.stats_deserialize(blob, planar_config(stream=s))
+    assert e.value.code == L.STATS_E_MISMATCH
+
+
+def test_table2_to_table3_on_gpu_eigensolver():
+    # Pins the GPU PCA stage on the paper's worked example: a checkpoint whose
+    # co-moments are the Table 2 matrix (n = 2, ddof = 1 gives cov = Table 2,
+    # a unit diagonal gives corr = Table 2) must give Table 3.
+    import struct
+    from golden_io import table2, table3
+    L = lib()
+    A = table2()
+    p = 10
+    T = p * (p + 1) // 2
+    cfg = aos_config(p=10, int_cols=[False] * 10, ident=(), stream=current_stream())
+    words = 2 + 2 * p + 2 * T + p + T
+    state = [0] * words
+    state[0] = 2
+    off_m2 = 2 + 2 * p + 2 * T + p
+    t = 0
+    for i in range(p):
+        for j in range(i, p):
+            state[off_m2 + t] = struct.unpack("<Q", struct.pack("<d", A[i, j]))[0]
+            t += 1
+    hdr = b"STSTATS1" + struct.pack("<q", p) + b"".join(struct.pack("<ii", L.STATS_F64, 0) for _ in range(p))
+    blob = hdr + b"".join(struct.pack("<Q", w) for w in state)
+    h = L.stats_deserialize(blob, cfg)
+    try:
+        fin = L.stats_finalize(h, 10)
+    finally:
+        L.stats_close(h)
+    assert np.array_equal(fin["corr"], A)
+    t3 = table3()
+    assert [float(f"{v:.6g}") for v in fin["eigval"]] == [float(s) for s in t3["eig_str"]]
+    assert [float(f"{v:.6g}") for v in fin["var_pct"]] == [float(s) for s in t3["var_str"]]
+    assert [float(f"{v:.6g}") for v in fin["cum_pct"]] == [float(s) for s in t3["cum_str"]]
+    for k in range(10):
+        s = 1.0 if fin["eigvec"][k] @ t3["loadings"][k] > 0 else -1.0
+        assert np.max(np.abs(s * fin["eigvec"][k] - t3["loadings"][k])) <= 5.1e-7
+    lam, vec = oracle.eig_sym(A)
+    assert np.max(np.abs(fin["eigval"] - lam)) <= 1e-14
