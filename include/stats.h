@@ -127,9 +127,12 @@ int stats_open(const stats_config* cfg, stats_ctx** out);
 
 /* Adds nrows rows.  planes[k] is the base of plane k (device address for
  * STATS_MEM_DEVICE; host address otherwise).  Device planes must be 16-byte
- * aligned.  HOST_PINNED input is copied through two pinned staging slots of
- * staging_rows rows with copies overlapping the reduction; pageable HOST
- * input is copied before return.  nrows == 0 is a no-op. */
+ * aligned.  Host input is streamed in chunks of staging_rows rows through two
+ * device staging slots, the copy of one chunk (on a second stream)
+ * overlapping the reduction of the previous one: HOST_PINNED input is copied
+ * by DMA straight from the caller's page-locked buffer; pageable HOST input is
+ * first copied by the CPU into two page-locked slots and may be reused once
+ * the call returns.  nrows == 0 is a no-op. */
 int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows, int32_t mem_kind);
 
 /* Adds the complete lines of a CSV text chunk: one row per line, p fields
@@ -154,6 +157,10 @@ int stats_accumulate_segmented(stats_ctx* h, const void* const* planes,
 /* dst := statistics of rows(dst) and rows(src); src unchanged.  Both must
  * have the same columns (else STATS_E_MISMATCH) and be single-group. */
 int stats_merge(stats_ctx* dst, const stats_ctx* src);
+
+/* Clears the statistics of the handle (all groups) so it can take a new
+ * dataset; buffers and configuration are kept.  Stream-ordered. */
+int stats_reset(stats_ctx* h);
 
 /* Waits for all work of the handle; reports a deferred STATS_E_INEXACT or
  * STATS_E_PARSE. */

@@ -80,6 +80,7 @@ _sig = {
     "stats_accumulate_segmented": [_vp, _vp, _vp, _i32],
     "stats_merge": [_vp, _vp],
     "stats_sync": [_vp],
+    "stats_reset": [_vp],
     "stats_raw": [_vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "stats_finalize": [_vp, ctypes.POINTER(FinalizeOpts), _vp, _vp, _vp, _vp, _vp, _vp, _vp, _vp],
     "stats_finalize_groups": [_vp, ctypes.POINTER(FinalizeOpts), _vp, _vp, _vp, _vp],
@@ -190,6 +191,10 @@ def stats_merge(dst: int, src: int) -> None:
 
 def stats_sync(h: int) -> None:
     _check(_lib.stats_sync(h))
+
+
+def stats_reset(h: int) -> None:
+    _check(_lib.stats_reset(h))
 
 
 def _i128_to_int(v: I128) -> int:

@@ -497,6 +497,18 @@ extern "C" int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t
   }
 }
 
+extern "C" int stats_reset(stats_ctx* h) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  DeviceGuard g(h->device);
+  const Layout L = Layout::make(h->p);
+  const size_t bytes = (size_t)L.words * 8 * (size_t)(h->ngroups > 0 ? h->ngroups : 1);
+  hipError_t e = hipMemsetAsync(h->state[h->cur], 0, bytes, h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->status_dev, 0, sizeof(DevStatus), h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "stats_reset");
+  return STATS_OK;
+}
+
 extern "C" int stats_sync(stats_ctx* h) {
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
