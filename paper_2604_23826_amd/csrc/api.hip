@@ -341,10 +341,11 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
   }
   const int64_t W = rec_words(p);
   const Layout L = Layout::make(p);
-  const int64_t max_blocks = 16384;
+  // at most 2^28 rows (and 16384 blocks) per launch: plane offsets stay 32-bit
+  const int64_t max_rows = std::max<int64_t>(R, std::min<int64_t>(16384 * R, ((int64_t)1 << 28) / R * R));
   int64_t done = 0;
   while (done < nrows) {
-    const int64_t rows = std::min(nrows - done, max_blocks * R);
+    const int64_t rows = std::min(nrows - done, max_rows);
     const int64_t nblocks = (rows + R - 1) / R;
     int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
     if (rc) return rc;
