@@ -82,7 +82,8 @@ enum { STATS_MEM_DEVICE = 0, STATS_MEM_HOST_PINNED = 1, STATS_MEM_HOST = 2 };
 enum {
   STATS_PREC_FP64 = 0,       /* FP64 throughout */
   STATS_PREC_SPLIT_BF16 = 1, /* BF16 slices on MFMA, FP32 windows, FP64 merge */
-  STATS_PREC_AUTO = 2        /* FP64 for p <= 16, split BF16 above */
+  STATS_PREC_AUTO = 2        /* p <= 16: FP64; wider: split BF16 when every
+                                column is FP32 or int32, else FP64 */
 };
 
 /* Configuration flags. */

@@ -5,14 +5,6 @@
 
 using namespace st;
 
-namespace st {
-int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrows) {
-  (void)h;
-  (void)planes;
-  (void)nrows;
-  return fail(STATS_E_ARG, "p > 16 is not supported by this build");
-}
-}  // namespace st
 
 extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
                                      int32_t is_last, int64_t* bytes_consumed) {

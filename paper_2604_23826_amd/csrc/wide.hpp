@@ -1,0 +1,41 @@
+// Wide-table (p > 16) kernels: shared definitions.
+#pragma once
+#include "common.hpp"
+
+namespace st {
+namespace wide {
+
+constexpr int kThreads = 256;
+constexpr int KR = 32;  // rows staged per step
+
+enum { MODE_FP64 = 0, MODE_SPLIT = 1 };
+
+// One column slot: element r at base + r * stride, of type kind (STATS_*).
+struct SlotInfo {
+  const char* base;
+  int64_t stride;
+  int32_t kind;
+  uint8_t chk;    // FP column flagged INTEGER: check values
+  uint8_t isint;  // integer column: shift stored as int64
+  uint8_t pad[2];
+};
+
+struct Args {
+  const SlotInfo* slots;  // p entries (device)
+  int p;
+  const int2* tiles;      // (A, B) super-group pairs with A <= B (device)
+  int ntiles;
+  int64_t nblocks;
+  int64_t nrows;
+  int64_t R;              // rows per block (multiple of KR)
+  uint64_t* rec;          // block records
+  DevStatus* status;
+};
+
+}  // namespace wide
+
+// st = super-group width (32 or 64); mode = MODE_FP64 or MODE_SPLIT.
+void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s);
+void launch_wide_split(const wide::Args& a, int st, hipStream_t s);
+
+}  // namespace st

@@ -1,0 +1,106 @@
+// Host side of the wide-table path: slot table, super-tile list, launch
+// splitting and the choice between FP64 and split-BF16 matrix-core modes.
+#include <algorithm>
+#include <vector>
+
+#include "common.hpp"
+#include "runtime.hpp"
+#include "wide.hpp"
+
+namespace st {
+
+// Split BF16 is used when asked for, or by default (PREC_AUTO) when every
+// column is stored as FP32 or int32 (FP32 values have 24 significant bits and
+// shifted int32 values below 2^26 pass the exactness guard, so the three
+// 9-bit digits hold them exactly within a block's range); otherwise FP64.
+static int wide_mode(const stats_ctx* h) {
+  if (h->precision == STATS_PREC_FP64) return wide::MODE_FP64;
+  if (h->precision == STATS_PREC_SPLIT_BF16) return wide::MODE_SPLIT;
+  for (const auto& c : h->cols)
+    if (c.dtype != STATS_F32 && c.dtype != STATS_I32) return wide::MODE_FP64;
+  return wide::MODE_SPLIT;
+}
+
+int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrows) {
+  const int p = h->p;
+  const int ST = p <= 32 ? 32 : 64;
+  const int ng = (p + ST - 1) / ST;
+  const int mode = wide_mode(h);
+  std::vector<int2> tiles;
+  for (int A = 0; A < ng; ++A)
+    for (int B = A; B < ng; ++B) tiles.push_back(make_int2(A, B));
+  int64_t R = h->block_rows;
+  if (!R) {
+    R = (nrows + 1023) / 1024;
+    R = (R + 1023) / 1024 * 1024;
+    R = std::max<int64_t>(1024, std::min<int64_t>(R, 32768));
+  }
+  const int64_t W = rec_words(p);
+  const Layout L = Layout::make(p);
+  // records of one launch stay below ~256 MB
+  const int64_t max_blocks = std::max<int64_t>(1, ((int64_t)256 << 20) / (W * 8));
+  const size_t slot_bytes = sizeof(wide::SlotInfo) * (size_t)p;
+  const size_t tile_bytes = sizeof(int2) * tiles.size();
+  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, tile_bytes + slot_bytes + 256);
+  if (rc) return rc;
+  int2* tiles_dev = (int2*)h->aux3_dev;
+  wide::SlotInfo* slots_dev = (wide::SlotInfo*)((char*)h->aux3_dev + (tile_bytes + 255) / 256 * 256);
+  hipError_t e = hipMemcpyAsync(tiles_dev, tiles.data(), tile_bytes, hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "uploading tile list");
+  std::vector<wide::SlotInfo> slots(p);
+  int64_t done = 0;
+  while (done < nrows) {
+    const int64_t rows = std::min(nrows - done, max_blocks * R);
+    const int64_t nblocks = (rows + R - 1) / R;
+    for (int c = 0; c < p; ++c) {
+      const stats_column& col = h->cols[c];
+      wide::SlotInfo& s = slots[c];
+      s.stride = h->row_stride[col.plane];
+      s.base = (const char*)planes[col.plane] + col.byte_offset + done * s.stride;
+      s.kind = col.dtype;
+      s.chk = (col.dtype == STATS_F32 || col.dtype == STATS_F64) && (col.flags & STATS_COL_INTEGER);
+      s.isint = h->intf[c];
+      s.pad[0] = s.pad[1] = 0;
+    }
+    // the previous launch has read the table before this copy is ordered after it
+    e = hipMemcpyAsync(slots_dev, slots.data(), slot_bytes, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
+    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    if (rc) return rc;
+    const int64_t l1_groups = (nblocks + 31) / 32;
+    rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
+    if (rc) return rc;
+    wide::Args a;
+    a.slots = slots_dev;
+    a.p = p;
+    a.tiles = tiles_dev;
+    a.ntiles = (int)tiles.size();
+    a.nblocks = nblocks;
+    a.nrows = rows;
+    a.R = R;
+    a.rec = h->rec;
+    a.status = h->status_dev;
+    {
+      Timer t;
+      t.begin(h, STATS_K_SYRK);
+      launch_wide(a, ST, mode, h->stream);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "wide kernel launch");
+    {
+      Timer t;
+      t.begin(h, STATS_K_MERGE);
+      launch_merge_records(h->rec, nblocks, p, 0, h->intf_dev, h->l1, l1_groups, h->state[h->cur],
+                           h->state[h->cur ^ 1], h->status_dev, h->stream);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "merge kernel launch");
+    h->cur ^= 1;
+    done += rows;
+  }
+  return STATS_OK;
+}
+
+}  // namespace st

@@ -1,0 +1,119 @@
+"""GPU parity of the wide-table path (p > 16, matrix cores) against the CPU
+oracle: FP64 mode (exact for integer columns) and split-BF16 mode (exact for
+integer columns, floating columns within 1e-9 correlation-scaled)."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from datagen import gauss
+from helpers import check_raw_against_oracle, corr_scaled_err, current_stream, lib, to_dev
+
+pytestmark = pytest.mark.gpu
+
+C4_INT = [True] * 8 + [False] + [True] * 23  # 10 Table-1 columns + 22 U{0..100}
+
+
+def _c4_config(L, **kw):
+    cols = [(L.STATS_F64, 0, 8 * c, (L.STATS_COL_INTEGER if C4_INT[c] else 0) |
+             (L.STATS_COL_IDENTIFIER if c == 0 else 0)) for c in range(32)]
+    return L.make_config(cols, [256], stream=current_stream(), **kw)
+
+
+def _run(L, cfg, planes, n, p, mask=None):
+    h = L.stats_open(cfg)
+    try:
+        L.stats_accumulate(h, planes, n)
+        raw = L.stats_raw(h, p)
+        fin = L.stats_finalize(h, p, mask=mask) if n > 1 else None
+    finally:
+        L.stats_close(h)
+    return raw, fin
+
+
+@pytest.mark.parametrize("n", [1, 2, 100, 4095, 70_001])
+@pytest.mark.parametrize("prec", ["fp64", "split"])
+def test_p32_table1_extended(n, prec):
+    """FP64 mode: everything to the narrow path's bar.  Split mode on FP64
+    input: integer columns still exact; the FP64 column cotC is rounded to 27
+    bits of its block range, so its entries carry ~1e-8 relative error."""
+    print(f"p32 n={n} {prec}", flush=True)
+    L = lib()
+    x = datagen.groups_aos(4, n, row0=0, a0=1)
+    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT_BF16
+    raw, fin = _run(L, _c4_config(L, precision=precision), [to_dev(x)], n, 32)
+    st = oracle.sufficient_stats(oracle.columns_of(x), C4_INT)
+    if prec == "fp64":
+        check_raw_against_oracle(raw, st, C4_INT)
+    else:
+        assert raw["n"] == n
+        for i in range(32):
+            for j in range(32):
+                a, b = min(i, j), max(i, j)
+                t = oracle.tri_index(32, a, b)
+                if C4_INT[a] and C4_INT[b]:
+                    assert raw["C_int"][i][j] == st.C_int[t], (i, j)
+                else:
+                    ref = float(st.C_exact[t])
+                    sc = (abs(float(st.C_exact[oracle.tri_index(32, a, a)])) *
+                          abs(float(st.C_exact[oracle.tri_index(32, b, b)]))) ** 0.5
+                    assert abs(raw["C_f64"][i, j] - ref) <= 1e-7 * sc + 1e-300, (i, j)
+    if n > 1:
+        ref = oracle.finalize(st, mask=range(1, 32))
+        sel = C4_INT[1:]
+        for a in range(31):
+            for b in range(31):
+                if sel[a] and sel[b]:
+                    assert fin["cov"][a, b] == ref["cov"][a, b]
+        tol = 1e-12 if prec == "fp64" else 1e-7
+        assert corr_scaled_err(fin["cov"], ref["cov"]) <= tol
+        assert np.max(np.abs(fin["eigval"] - ref["eigval"])) <= tol * np.max(ref["eigval"])
+
+
+def _c3_config(L, p, **kw):
+    # column 0: int32 identifier (plane 1); columns 1..p-1: FP32 row-major (plane 0)
+    cols = [(L.STATS_I32, 1, 0, L.STATS_COL_IDENTIFIER)] + \
+           [(L.STATS_F32, 0, 4 * j, 0) for j in range(p - 1)]
+    return L.make_config(cols, [4 * (p - 1), 4], stream=current_stream(), **kw)
+
+
+@pytest.mark.parametrize("p", [17, 33, 65, 257])
+@pytest.mark.parametrize("prec", ["fp64", "split"])
+def test_gaussian_fp32_with_identifier(p, prec):
+    n = 20_011 if p < 257 else 9_001
+    print(f"gauss p={p} n={n} {prec}", flush=True)
+    L = lib()
+    x = gauss.rows_host(3, n, p - 1)
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT_BF16
+    raw, fin = _run(L, _c3_config(L, p, precision=precision, block_rows=4096),
+                    [to_dev(x), to_dev(ident)], n, p)
+    is_int = [True] + [False] * (p - 1)
+    cols = [ident] + [x[:, j] for j in range(p - 1)]
+    st = oracle.sufficient_stats(cols, is_int)
+    assert raw["n"] == n
+    assert raw["s_int"][0] == n * (n + 1) // 2
+    assert raw["C_int"][0][0] == n * (n + 1) * (2 * n + 1) // 6
+    ref = oracle.finalize(st, mask=range(1, p))
+    err = corr_scaled_err(fin["cov"], ref["cov"])
+    print(f"  cov err {err:.2e}", flush=True)
+    assert err <= (1e-12 if prec == "fp64" else 1e-9)
+    lam_err = np.max(np.abs(fin["eigval"] - ref["eigval"])) / np.max(ref["eigval"])
+    assert lam_err <= (1e-12 if prec == "fp64" else 1e-9)
+    # raw cross products of the identifier with every column
+    for j in range(1, p):
+        ref_c = float(st.C_exact[oracle.tri_index(p, 0, j)])
+        assert abs(raw["C_f64"][0, j] - ref_c) <= 1e-9 * abs(ref_c)
+
+
+def test_split_and_fp64_agree_and_split_is_exact_on_fp32_grid():
+    L = lib()
+    p, n = 65, 30_000
+    x = gauss.rows_host(5, n, p - 1)
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    planes = [to_dev(x), to_dev(ident)]
+    _, f64 = _run(L, _c3_config(L, p, precision=L.STATS_PREC_FP64), planes, n, p)
+    _, spl = _run(L, _c3_config(L, p, precision=L.STATS_PREC_SPLIT_BF16), planes, n, p)
+    # C3-like FP32 data is shifted within its binade: the digits are exact, so
+    # the two modes differ only by FP64 summation order
+    assert corr_scaled_err(spl["cov"], f64["cov"]) <= 1e-13
