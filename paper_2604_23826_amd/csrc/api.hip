@@ -276,6 +276,7 @@ extern "C" void stats_close(stats_ctx* h) {
   if (h->graph_exec) (void)hipGraphExecDestroy(h->graph_exec);
   if (h->graph) (void)hipGraphDestroy(h->graph);
   if (h->copy_stream) (void)hipStreamDestroy(h->copy_stream);
+  if (h->cap_stream) (void)hipStreamDestroy(h->cap_stream);
   if (h->own_stream && h->stream) (void)hipStreamDestroy(h->stream);
   delete h;
 }

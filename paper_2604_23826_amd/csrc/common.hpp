@@ -264,6 +264,26 @@ __host__ __device__ inline U256 i256_mul_sub(i128 a, i128 b, i128 c, i128 d, boo
   return u256_sub(y, x);
 }
 
+// Covariance of integer columns i <= j from the exact totals: the 256-bit
+// numerator n C_ij - s_i s_j over n (n - ddof), correctly rounded.
+__device__ inline double exact_cov(const uint64_t* st, const Layout& L, int i, int j, int64_t n,
+                                   int ddof) {
+  const i128 si = load_i128(st + L.off_s + 2 * i);
+  const i128 sj = load_i128(st + L.off_s + 2 * j);
+  const i128 cij = load_i128(st + L.off_C + 2 * tri(L.p, i, j));
+  bool neg;
+  U256 num = i256_mul_sub((i128)n, cij, si, sj, &neg);  // n C_ij - s_i s_j
+  const U256 den = u256_mul128((u128)n, (u128)(n - ddof));
+  return u256_div_to_double(neg, num, den);
+}
+
+// Mean of an integer column, s_i / n correctly rounded.
+__device__ inline double exact_mean(const uint64_t* st, const Layout& L, int i, int64_t n) {
+  bool neg;
+  const u128 m = abs128(load_i128(st + L.off_s + 2 * i), &neg);
+  return u256_div_to_double(neg, u256_from_u128(m), u256_from_u128((u128)n));
+}
+
 // ---- kernel launchers (defined in the .hip files) ----------------------------
 
 struct AccumLaunch {

@@ -36,23 +36,6 @@ struct Args {
   double* scratch;
 };
 
-__device__ inline double exact_cov(const uint64_t* st, const Layout& L, int i, int j, int64_t n,
-                                   int ddof) {
-  const i128 si = load_i128(st + L.off_s + 2 * i);
-  const i128 sj = load_i128(st + L.off_s + 2 * j);
-  const i128 cij = load_i128(st + L.off_C + 2 * tri(L.p, i, j));
-  bool neg;
-  U256 num = i256_mul_sub((i128)n, cij, si, sj, &neg);  // n C_ij - s_i s_j
-  const U256 den = u256_mul128((u128)n, (u128)(n - ddof));
-  return u256_div_to_double(neg, num, den);
-}
-
-__device__ inline double exact_mean(const uint64_t* st, const Layout& L, int i, int64_t n) {
-  bool neg;
-  const u128 m = abs128(load_i128(st + L.off_s + 2 * i), &neg);
-  return u256_div_to_double(neg, u256_from_u128(m), u256_from_u128((u128)n));
-}
-
 // Round-robin schedule on m (even) players: player at position pos in round r.
 __device__ inline int rr_player(int pos, int r, int m) {
   return pos == 0 ? 0 : ((pos - 1 + r) % (m - 1)) + 1;

@@ -61,6 +61,11 @@ struct stats_ctx {
   // segmented launch graph
   hipGraph_t graph = nullptr;
   hipGraphExec_t graph_exec = nullptr;
+  hipStream_t cap_stream = nullptr;
+  int graph_nwg = 0;
+  int64_t seg_tile_rows = 0;
+  int seg_wg_per_cu = 0;
+  int64_t seg_cap_rt = 0;
 
   // kernel timing (STATS_CFG_TIMING)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[STATS_K_COUNT];
@@ -79,6 +84,9 @@ int sync_handle(stats_ctx* h);
 void collect_timings(stats_ctx* h);
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows);
 int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrows);
+int raw_of_state(stats_ctx* h, const uint64_t* state_dev, int64_t* n, stats_i128* s_int,
+                 double* s_f64, stats_i128* C_int, double* C_f64, uint8_t* exact_mask);
+int selection(const stats_ctx* h, const stats_finalize_opts* o, std::vector<int32_t>* sel);
 
 struct DeviceGuard {
   int prev = -1;

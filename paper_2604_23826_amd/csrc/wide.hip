@@ -47,8 +47,10 @@ __device__ inline double load_shifted(const SlotInfo& si, int64_t r, double K, i
   }
 }
 
+// One block of rows [r0, r1) and super-tile (A, B): shifts, staged FP64
+// values, MFMA sub-tiles, and this super-tile's part of the record at out.
 template <int ST>
-__global__ __launch_bounds__(kThreads) void k_wide_f64(Args a) {
+__device__ void wide_f64_block(const Args& a, uint64_t* out, int64_t r0, int64_t r1, int A, int B) {
   constexpr int NSUB = ST / 16;       // sub-tiles per super-group side
   constexpr int MAXW = (NSUB * NSUB + 3) / 4;  // sub-tiles per wave
   __shared__ double sD[KR][2 * ST + 1];
@@ -56,16 +58,8 @@ __global__ __launch_bounds__(kThreads) void k_wide_f64(Args a) {
   __shared__ int64_t sKi[2 * ST];
   __shared__ double sS[2 * ST];
 
-  // block / super-tile from the XCD-aware id
-  const int64_t id = blockIdx.x;
-  const int64_t xcd = id % 8, y = id / 8;
-  const int t = (int)(y % a.ntiles);
-  const int64_t b = (y / a.ntiles) * 8 + xcd;
-  if (b >= a.nblocks) return;
-  const int A = a.tiles[t].x, B = a.tiles[t].y;
   const bool diag = A == B;
   const int nsl = diag ? ST : 2 * ST;  // staged slots
-  const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
 
   // shifts of the staged slots
   for (int s = threadIdx.x; s < nsl; s += kThreads) {
@@ -154,7 +148,6 @@ __global__ __launch_bounds__(kThreads) void k_wide_f64(Args a) {
 
   // ---- write this super-tile's part of the block record ----
   const int p = a.p;
-  uint64_t* out = a.rec + b * rec_words(p);
 #pragma unroll
   for (int u = 0; u < MAXW; ++u) {
     if (u >= nmine) continue;
@@ -198,6 +191,40 @@ __global__ __launch_bounds__(kThreads) void k_wide_f64(Args a) {
   }
 }
 
+template <int ST>
+__global__ __launch_bounds__(kThreads) void k_wide_f64(Args a) {
+  // block / super-tile from the XCD-aware id
+  const int64_t id = blockIdx.x;
+  const int64_t xcd = id % 8, y = id / 8;
+  const int t = (int)(y % a.ntiles);
+  const int64_t b = (y / a.ntiles) * 8 + xcd;
+  if (b >= a.nblocks) return;
+  const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
+  wide_f64_block<ST>(a, a.rec + b * rec_words(a.p), r0, r1, a.tiles[t].x, a.tiles[t].y);
+}
+
+// Persistent variant for batched groups: workgroups take (row tile,
+// super-tile) items from an atomic queue until it is empty; record slots are
+// indexed by row tile, so results do not depend on which workgroup ran what.
+template <int ST>
+__global__ __launch_bounds__(kThreads) void k_seg_f64(Args a, SegArgs g) {
+  __shared__ int64_t s_item;
+  const int64_t nitems = *g.nrowtiles * a.ntiles;
+  for (;;) {
+    __syncthreads();  // previous item's LDS use is over
+    if (threadIdx.x == 0) s_item = (int64_t)atomicAdd(g.counter, 1ull);
+    __syncthreads();
+    const int64_t item = s_item;
+    if (item >= nitems) break;
+    const int64_t rt = item / a.ntiles;
+    const int t = (int)(item % a.ntiles);
+    const SegTile tile = g.rowtiles[rt];
+    wide_f64_block<ST>(a, a.rec + rt * rec_words(a.p), tile.r0, tile.r1, a.tiles[t].x, a.tiles[t].y);
+  }
+}
+
+__global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
+
 }  // namespace wide
 
 void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s) {
@@ -209,6 +236,12 @@ void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s) {
   }
   if (st == 32) hipLaunchKernelGGL(wide::k_wide_f64<32>, grid, block, 0, s, a);
   else hipLaunchKernelGGL(wide::k_wide_f64<64>, grid, block, 0, s, a);
+}
+
+void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s) {
+  hipLaunchKernelGGL(wide::k_zero_counter, dim3(1), dim3(1), 0, s, g.counter);
+  if (st == 32) hipLaunchKernelGGL(wide::k_seg_f64<32>, dim3(nwg), dim3(wide::kThreads), 0, s, a, g);
+  else hipLaunchKernelGGL(wide::k_seg_f64<64>, dim3(nwg), dim3(wide::kThreads), 0, s, a, g);
 }
 
 }  // namespace st

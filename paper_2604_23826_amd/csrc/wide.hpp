@@ -32,7 +32,24 @@ struct Args {
   DevStatus* status;
 };
 
+// Batched groups: row tile [r0, r1) of group `group` (rows relative to the
+// planes' base).
+struct SegTile {
+  int64_t r0, r1;
+  int32_t group;
+  int32_t pad;
+};
+
+struct SegArgs {
+  const SegTile* rowtiles;            // row tiles, sorted by group (device)
+  const int64_t* nrowtiles;           // number of row tiles (device word)
+  unsigned long long* counter;        // work queue head (device word)
+};
+
 }  // namespace wide
+
+// Persistent segmented launch (zeroes the queue first): nwg workgroups.
+void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s);
 
 // st = super-group width (32 or 64); mode = MODE_FP64 or MODE_SPLIT.
 void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s);
