@@ -107,6 +107,12 @@ void collect_timings(stats_ctx* h) {
   }
 }
 
+// Zero status bits; the smallest-parse-error offset starts at the maximum.
+hipError_t clear_status(stats_ctx* h) {
+  static const DevStatus init = {0u, 0u, ~0ull};
+  return hipMemcpyAsync(h->status_dev, &init, sizeof init, hipMemcpyHostToDevice, h->stream);
+}
+
 int check_status(stats_ctx* h) {
   DevStatus s;
   hipError_t e = hipMemcpy(&s, h->status_dev, sizeof s, hipMemcpyDeviceToHost);
@@ -231,7 +237,7 @@ int open_handle(const stats_config* cfg, int ngroups, stats_ctx** out) {
   }
   hipError_t e = hipMemcpyAsync(h->intf_dev, h->intf.data(), (size_t)h->p, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemsetAsync(h->state[0], 0, (size_t)(L.words * 8 * nstates), h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->status_dev, 0, sizeof(DevStatus), h->stream);
+  if (e == hipSuccess) e = clear_status(h);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
     int r = hip_fail(h, e, "initialising handle state");
@@ -506,8 +512,9 @@ extern "C" int stats_reset(stats_ctx* h) {
   const Layout L = Layout::make(h->p);
   const size_t bytes = (size_t)L.words * 8 * (size_t)(h->ngroups > 0 ? h->ngroups : 1);
   hipError_t e = hipMemsetAsync(h->state[h->cur], 0, bytes, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->status_dev, 0, sizeof(DevStatus), h->stream);
+  if (e == hipSuccess) e = clear_status(h);
   if (e != hipSuccess) return hip_fail(h, e, "stats_reset");
+  h->text_offset = 0;
   return STATS_OK;
 }
 

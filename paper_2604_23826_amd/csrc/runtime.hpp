@@ -67,6 +67,9 @@ struct stats_ctx {
   int seg_wg_per_cu = 0;
   int64_t seg_cap_rt = 0;
 
+  // text ingest: bytes consumed so far (offsets in parse errors)
+  int64_t text_offset = 0;
+
   // kernel timing (STATS_CFG_TIMING)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[STATS_K_COUNT];
   int64_t kt_n[STATS_K_COUNT] = {};
@@ -87,6 +90,7 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
 int raw_of_state(stats_ctx* h, const uint64_t* state_dev, int64_t* n, stats_i128* s_int,
                  double* s_f64, stats_i128* C_int, double* C_f64, uint8_t* exact_mask);
 int selection(const stats_ctx* h, const stats_finalize_opts* o, std::vector<int32_t>* sel);
+hipError_t clear_status(stats_ctx* h);
 
 struct DeviceGuard {
   int prev = -1;

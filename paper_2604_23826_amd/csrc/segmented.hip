@@ -384,7 +384,7 @@ static int autotune(stats_ctx* h, const void* const* planes, const int64_t* off,
   // the timing runs left garbage in the status word only through real
   // exactness violations, which the real run reports as well: clear it
   if (!rc) {
-    hipError_t e = hipMemsetAsync(h->status_dev, 0, sizeof(DevStatus), h->stream);
+    hipError_t e = clear_status(h);
     if (e != hipSuccess) rc = hip_fail(h, e, "autotune reset");
   }
   return rc;

@@ -1,0 +1,481 @@
+// Text ingest fused with the reduction (p <= 16).
+//
+// The data start as CSV text (section "Validation and Infrastructure
+// Testing"; section "Data Representation and Sufficient Statistics" on the
+// cost of repeated parsing).  Here a chunk of text in HBM is parsed once, on
+// the GPU, and every parsed row goes straight into the same shifted column
+// sums and X^T X accumulators as the binary path; nothing is written back.
+//
+// Work split: workgroup w owns the lines whose first byte lies in
+// [w * SEG, (w + 1) * SEG); within it, thread t owns the lines starting in its
+// 256-byte slice.  The workgroup stages its bytes (plus MAXLINE bytes of the
+// next segment, for lines that run past the end) in LDS with 4 bytes of
+// padding per 256 so that threads reading their own slices hit different
+// banks.  The block shift is the workgroup's first line.
+//
+// Fields: integer columns are decimal integers (optional sign, at most 18
+// digits), parsed exactly; other columns are decimal numbers (optional sign,
+// digits with an optional point, optional exponent), converted to the nearest
+// FP64 value: the decimal significand w and exponent q give w * 10^q, formed
+// as an exact 256-bit integer ratio and divided once with correct rounding
+// (values between about 1e-57 and 1e75).  A malformed field marks
+// the handle (STATS_E_PARSE, smallest byte offset) and its row is skipped.
+#include <cstring>
+
+#include "accum_impl.hpp"
+#include "runtime.hpp"
+
+namespace st {
+namespace text {
+
+constexpr int kThreads = 256;
+constexpr int SEG = 1 << 16;     // bytes of line starts per workgroup
+constexpr int MAXLINE = 4096;    // longest line accepted
+constexpr int SLICE = 256;       // bytes of line starts per thread
+constexpr int STAGE = 16 + SEG + MAXLINE;
+constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 1) * 4;
+
+struct Args {
+  const char* buf;
+  int64_t nbytes;  // readable bytes
+  int64_t nend;    // lines start before nend; the last one may end at nend
+  int p;
+  uint32_t intmask;
+  int64_t base_off;  // offset of buf in the caller's stream (for messages)
+  acc::Args acc;
+  DevStatus* status;
+};
+
+__device__ inline int pad(int i) { return i + ((i >> 8) << 2); }
+
+struct Stage {
+  const unsigned char* s;
+  int64_t w0;  // stream offset of staged byte 0
+  int n;       // staged bytes
+  __device__ inline int at(int64_t pos) const {
+    const int64_t i = pos - w0;
+    return (i >= 0 && i < n) ? s[pad((int)i)] : -1;
+  }
+};
+
+__device__ inline U256 u256_mul_small(U256 a, uint32_t m) {
+  U256 r;
+  u128 carry = 0;
+  for (int k = 0; k < 4; ++k) {
+    const u128 t = (u128)a.w[k] * m + carry;
+    r.w[k] = (uint64_t)t;
+    carry = t >> 64;
+  }
+  return r;
+}
+
+// Decimal text [b, e) -> nearest FP64.  Returns false on malformed input or
+// a value outside the supported range.  The first 38 significant digits are
+// kept exactly (128 bits); any further nonzero digit is kept as a sticky
+// digit 1 appended to them, which places the value strictly between two
+// 38-digit neighbours and rounds like the full expansion whenever no FP64
+// rounding midpoint lies that close (always, e.g., for printed doubles).
+__device__ inline bool parse_decimal(const Stage& S, int64_t b, int64_t e, double* out) {
+  int64_t i = b;
+  bool neg = false;
+  int c = S.at(i);
+  if (c == '-' || c == '+') {
+    neg = c == '-';
+    ++i;
+  }
+  u128 w = 0;
+  int nd = 0;
+  int64_t q = 0;
+  bool digits = false, sticky = false;
+  for (; i < e; ++i) {
+    c = S.at(i);
+    if (c < '0' || c > '9') break;
+    digits = true;
+    const int d = c - '0';
+    if (w == 0 && d == 0) continue;
+    if (nd < 38) {
+      w = w * 10 + (u128)d;
+      ++nd;
+    } else {
+      sticky |= d != 0;
+      ++q;
+    }
+  }
+  if (i < e && S.at(i) == '.') {
+    for (++i; i < e; ++i) {
+      c = S.at(i);
+      if (c < '0' || c > '9') break;
+      digits = true;
+      const int d = c - '0';
+      if (w == 0 && d == 0) {
+        --q;
+        continue;
+      }
+      if (nd < 38) {
+        w = w * 10 + (u128)d;
+        ++nd;
+        --q;
+      } else {
+        sticky |= d != 0;
+      }
+    }
+  }
+  if (!digits) return false;
+  if (i < e && (S.at(i) == 'e' || S.at(i) == 'E')) {
+    ++i;
+    bool eneg = false;
+    c = S.at(i);
+    if (c == '-' || c == '+') {
+      eneg = c == '-';
+      ++i;
+    }
+    int64_t ex = 0;
+    bool ed = false;
+    for (; i < e; ++i) {
+      c = S.at(i);
+      if (c < '0' || c > '9') break;
+      ed = true;
+      if (ex < 100000) ex = ex * 10 + (c - '0');
+    }
+    if (!ed) return false;
+    q += eneg ? -ex : ex;
+  }
+  if (i != e) return false;
+  if (w == 0) {
+    *out = neg ? -0.0 : 0.0;
+    return true;
+  }
+  U256 num = u256_from_u128(w), den = u256_from_u128((u128)1);
+  if (sticky) {
+    num = u256_mul_small(num, 10u);
+    num.w[0] |= 1u;  // (10 w + 1) 10^(q - 1); the low digit was 0
+    --q;
+  }
+  // range: the exact ratio must fit the 256-bit division
+  const int lw = u256_bitlen(num);
+  if (q >= 0) {
+    if (lw + (q * 3402 + 1023) / 1024 > 250) return false;  // log2(10) < 3402/1024
+    for (int k = 0; k < q; ++k) num = u256_mul_small(num, 10u);
+  } else {
+    if (-q > 57) return false;
+    for (int k = 0; k < -q; ++k) den = u256_mul_small(den, 10u);
+  }
+  *out = u256_div_to_double(neg, num, den);
+  return true;
+}
+
+// Decimal integer text [b, e) (at most 18 digits).
+__device__ inline bool parse_integer(const Stage& S, int64_t b, int64_t e, int64_t* out) {
+  int64_t i = b;
+  bool neg = false;
+  int c = S.at(i);
+  if (c == '-' || c == '+') {
+    neg = c == '-';
+    ++i;
+  }
+  if (i >= e) return false;
+  int64_t v = 0;
+  int nd = 0;
+  for (; i < e; ++i) {
+    c = S.at(i);
+    if (c < '0' || c > '9') return false;
+    if (++nd > 18) return false;
+    v = v * 10 + (c - '0');
+  }
+  *out = neg ? -v : v;
+  return true;
+}
+
+// Parses the line starting at L (p fields).  Returns the end position (the
+// '\n' or nend), or -1 on a malformed line (*bad_at = offending field).
+template <int P>
+__device__ inline int64_t parse_line(const Args& a, const Stage& S, int64_t L, double (&x)[P],
+                                     int64_t (&xi)[P], int64_t* bad_at) {
+  int64_t f0 = L;
+  bool ok = true;
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    int64_t f1 = f0;
+    int ch = S.at(f1);
+    while (ch >= 0 && ch != ',' && ch != '\n' && f1 < a.nend) {
+      ++f1;
+      ch = S.at(f1);
+    }
+    const bool last = (c == P - 1);
+    const bool term_ok = last ? (ch == '\n' || f1 >= a.nend) : (ch == ',');
+    if (ch < 0 && f1 < a.nend) {  // ran past the staged bytes: line too long
+      *bad_at = f0;
+      return -1;
+    }
+    if (ok) {
+      if (!term_ok || f1 == f0) {
+        ok = false;
+        *bad_at = f0;
+      } else if ((a.intmask >> c) & 1u) {
+        int64_t v;
+        if (parse_integer(S, f0, f1, &v)) {
+          xi[c] = v;
+          x[c] = (double)v;
+        } else {
+          ok = false;
+          *bad_at = f0;
+        }
+      } else {
+        double v;
+        if (parse_decimal(S, f0, f1, &v)) {
+          x[c] = v;
+          xi[c] = 0;
+        } else {
+          ok = false;
+          *bad_at = f0;
+        }
+      }
+    }
+    if (!ok) {
+      // skip to the end of the line
+      while (ch >= 0 && ch != '\n' && f1 < a.nend) {
+        ++f1;
+        ch = S.at(f1);
+      }
+      return -1 - f1;  // encoded end for the caller's scan (always < -1)
+    }
+    f0 = f1 + 1;
+    if (last) return f1;
+  }
+  return f0;
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_text(Args a) {
+  __shared__ unsigned char s_buf[STAGE_PADDED];
+  __shared__ double sK[P];
+  __shared__ int64_t sKi[P];
+  __shared__ unsigned long long s_n;
+  const int64_t s0 = (int64_t)blockIdx.x * SEG;
+  const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
+  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
+  const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
+  const int n = (int)(w1 - w0);
+  // stage [w0, w1): 16-byte loads where whole, bytes at the tail
+  const int nvec = n / 16;
+  for (int v = threadIdx.x; v < nvec; v += kThreads) {
+    const uint4 q = *(const uint4*)(a.buf + w0 + 16 * v);
+    const unsigned char* qb = (const unsigned char*)&q;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) s_buf[pad(16 * v + k)] = qb[k];
+  }
+  for (int k = 16 * nvec + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const Stage S{s_buf, w0, n};
+
+  // block shift: the first line starting in [s0, s1)
+  if (threadIdx.x == 0) {
+    int64_t L = s0;
+    if (s0 > 0) {
+      while (L < s1 && S.at(L - 1) != '\n') ++L;
+    }
+    double x[P];
+    int64_t xi[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      x[c] = 0.0;
+      xi[c] = 0;
+    }
+    int64_t bad_at;
+    if (L < s1) (void)parse_line<P>(a, S, L, x, xi, &bad_at);
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      sK[c] = ((a.intmask >> c) & 1u) ? (double)xi[c] : x[c];
+      sKi[c] = xi[c];
+    }
+  }
+  __syncthreads();
+  double K[P];
+  int64_t Ki[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    K[c] = sK[c];
+    Ki[c] = sKi[c];
+  }
+
+  acc::Acc<P> A;
+  A.zero();
+  uint32_t bad = 0;
+  unsigned long long nrows = 0;
+  int64_t first_bad = INT64_MAX;
+  const int64_t t0 = s0 + (int64_t)threadIdx.x * SLICE;
+  const int64_t t1 = min(t0 + SLICE, s1);
+  int64_t L = t0;
+  while (L < t1) {
+    if (L > 0 && S.at(L - 1) != '\n') {
+      ++L;
+      continue;
+    }
+    double x[P];
+    int64_t xi[P];
+    int64_t bad_at = INT64_MAX;
+    const int64_t end = parse_line<P>(a, S, L, x, xi, &bad_at);
+    if (end >= 0) {
+      double d[P];
+#pragma unroll
+      for (int c = 0; c < P; ++c)
+        d[c] = ((a.intmask >> c) & 1u) ? (double)(xi[c] - Ki[c]) : x[c] - K[c];
+      A.add(d);
+      ++nrows;
+      L = end + 1;
+    } else {
+      first_bad = min(first_bad, bad_at);
+      L = (end < -1) ? (-1 - end) + 1 : L + 1;
+    }
+  }
+  if (first_bad != INT64_MAX) {
+    atomicMin(&a.status->parse_off, (unsigned long long)(a.base_off + first_bad));
+    atomicOr(&a.status->bits, ST_PARSE);
+  }
+  atomicAdd(&s_n, nrows);
+  __syncthreads();
+  acc::finish_block<P>(a.acc, A, K, Ki, bad, 0, (int64_t)s_n);
+}
+
+// Position after the last '\n' in [0, n), or 0 when there is none; one
+// workgroup scans backwards in 64 KB windows.
+__global__ void k_last_newline(const char* buf, int64_t n, int64_t* out) {
+  __shared__ unsigned long long best;
+  if (threadIdx.x == 0) best = 0;
+  __syncthreads();
+  for (int64_t hi = n; hi > 0; hi -= SEG) {
+    const int64_t lo = hi > SEG ? hi - SEG : 0;
+    for (int64_t i = lo + threadIdx.x; i < hi; i += blockDim.x)
+      if (buf[i] == '\n') atomicMax(&best, (unsigned long long)(i + 1));
+    __syncthreads();
+    if (best > 0) break;
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) *out = (int64_t)best;
+}
+
+template <int P>
+void launch_text_p(const Args& a, int64_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_text<P>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
+}
+
+}  // namespace text
+
+using namespace text;
+
+static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t nend, int64_t base_off) {
+  const int p = h->p;
+  const int64_t nblocks = (nend + SEG - 1) / SEG;
+  if (nblocks == 0) return STATS_OK;
+  const int64_t W = rec_words(p);
+  const Layout L = Layout::make(p);
+  int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+  if (rc) return rc;
+  const int64_t l1_groups = (nblocks + 31) / 32;
+  rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
+  if (rc) return rc;
+  Args a;
+  memset(&a, 0, sizeof a);
+  a.buf = dbuf;
+  a.nbytes = nbytes;
+  a.nend = nend;
+  a.p = p;
+  a.base_off = base_off;
+  a.status = h->status_dev;
+  uint32_t intmask = 0;
+  for (int c = 0; c < p; ++c)
+    if (h->intf[c]) intmask |= 1u << c;
+  a.intmask = intmask;
+  acc::Args& x = a.acc;
+  for (int c = 0; c < 16; ++c) {
+    x.dtype[c] = (c < p && h->intf[c]) ? STATS_I64 : STATS_F64;
+    x.kdst[c] = (int8_t)(c < p ? c : 0);
+  }
+  x.intmask = intmask;
+  x.chkmask = 0;
+  int e = p;
+  for (int i = 0; i < p; ++i) x.dst[i] = (int16_t)i;
+  for (int i = 0; i < p; ++i)
+    for (int j = i; j < p; ++j) x.dst[e++] = (int16_t)(p + tri(p, i, j));
+  x.rec = h->rec;
+  {
+    Timer t;
+    t.begin(h, STATS_K_TEXT);
+    switch (p) {
+#define ST_CASE(PP) \
+  case PP: launch_text_p<PP>(a, nblocks, h->stream); break;
+      ST_CASE(1) ST_CASE(2) ST_CASE(3) ST_CASE(4) ST_CASE(5) ST_CASE(6) ST_CASE(7) ST_CASE(8)
+      ST_CASE(9) ST_CASE(10) ST_CASE(11) ST_CASE(12) ST_CASE(13) ST_CASE(14) ST_CASE(15) ST_CASE(16)
+#undef ST_CASE
+    }
+    t.end();
+  }
+  hipError_t err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(h, err, "text kernel launch");
+  {
+    Timer t;
+    t.begin(h, STATS_K_MERGE);
+    launch_merge_records(h->rec, nblocks, p, intmask, h->intf_dev, h->l1, l1_groups,
+                         h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+    t.end();
+  }
+  err = hipGetLastError();
+  if (err != hipSuccess) return hip_fail(h, err, "merge kernel launch");
+  h->cur ^= 1;
+  return STATS_OK;
+}
+
+}  // namespace st
+
+using namespace st;
+
+extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
+                                     int32_t is_last, int64_t* bytes_consumed) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: text input is not supported");
+  if (!bytes_consumed) return fail(STATS_E_ARG, "bytes_consumed is NULL");
+  *bytes_consumed = 0;
+  if (nbytes < 0) return fail(STATS_E_ARG, "nbytes < 0");
+  if (h->p > 16) return fail(STATS_E_ARG, "text ingest supports p <= 16");
+  if (nbytes == 0) return STATS_OK;
+  if (!buf) return fail(STATS_E_ARG, "buf is NULL");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(STATS_E_HIP, "hipSetDevice failed");
+  const char* dbuf = buf;
+  hipError_t e;
+  if (mem_kind == STATS_MEM_HOST || mem_kind == STATS_MEM_HOST_PINNED) {
+    int rc = ensure_dev(h, &h->aux_dev, &h->aux_cap, (size_t)nbytes);
+    if (rc) return rc;
+    e = hipMemcpyAsync(h->aux_dev, buf, (size_t)nbytes, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copying text to the device");
+    dbuf = (const char*)h->aux_dev;
+  } else if (mem_kind != STATS_MEM_DEVICE) {
+    return fail(STATS_E_ARG, "unknown mem_kind");
+  } else if ((uintptr_t)buf % 16 != 0) {
+    return fail(STATS_E_ARG, "device text buffers must be 16-byte aligned");
+  }
+  int64_t nend = nbytes;
+  if (!is_last) {
+    int rc = ensure_dev(h, (void**)&h->raw_out, &h->raw_cap, 64);
+    if (rc) return rc;
+    hipLaunchKernelGGL(k_last_newline, dim3(1), dim3(1024), 0, h->stream, dbuf, nbytes,
+                       (int64_t*)h->raw_out);
+    e = hipGetLastError();
+    if (e == hipSuccess)
+      e = hipMemcpyAsync(&nend, h->raw_out, 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "finding the last line end");
+  }
+  const int64_t base_off = h->text_offset;
+  int rc = text_launch(h, dbuf, nbytes, nend, base_off);
+  if (rc) return rc;
+  if (mem_kind != STATS_MEM_DEVICE) {
+    e = hipStreamSynchronize(h->stream);  // the staging copy may be reused by the next call
+    if (e != hipSuccess) return hip_fail(h, e, "text ingest");
+  }
+  h->text_offset += nend;
+  *bytes_consumed = nend;
+  return STATS_OK;
+}
