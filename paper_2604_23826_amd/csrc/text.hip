@@ -256,15 +256,25 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
   const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
   const int n = (int)(w1 - w0);
-  // stage [w0, w1): 16-byte loads where whole, bytes at the tail
-  const int nvec = n / 16;
-  for (int v = threadIdx.x; v < nvec; v += kThreads) {
-    const uint4 q = *(const uint4*)(a.buf + w0 + 16 * v);
-    const unsigned char* qb = (const unsigned char*)&q;
+  // stage [w0, w1): aligned 16-byte loads in the middle, single bytes at the
+  // two ragged ends, so that no byte outside [buf, buf + nbytes) is read
+  const uintptr_t lo = (uintptr_t)(a.buf + w0), hi = (uintptr_t)(a.buf + w1);
+  const uintptr_t alo = (lo + 15) & ~(uintptr_t)15, ahi = hi & ~(uintptr_t)15;
+  if (alo < ahi) {
+    const int head = (int)(alo - lo);
+    const int nvec = (int)((ahi - alo) / 16);
+    for (int v = threadIdx.x; v < nvec; v += kThreads) {
+      const uint4 q = *(const uint4*)(alo + 16 * (uintptr_t)v);
+      const unsigned char* qb = (const unsigned char*)&q;
 #pragma unroll
-    for (int k = 0; k < 16; ++k) s_buf[pad(16 * v + k)] = qb[k];
+      for (int k = 0; k < 16; ++k) s_buf[pad(head + 16 * v + k)] = qb[k];
+    }
+    for (int k = threadIdx.x; k < head; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+    const int tail0 = head + 16 * nvec;
+    for (int k = tail0 + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+  } else {
+    for (int k = threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
   }
-  for (int k = 16 * nvec + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   const Stage S{s_buf, w0, n};
@@ -453,8 +463,6 @@ extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbyt
     dbuf = (const char*)h->aux_dev;
   } else if (mem_kind != STATS_MEM_DEVICE) {
     return fail(STATS_E_ARG, "unknown mem_kind");
-  } else if ((uintptr_t)buf % 16 != 0) {
-    return fail(STATS_E_ARG, "device text buffers must be 16-byte aligned");
   }
   int64_t nend = nbytes;
   if (!is_last) {

@@ -126,6 +126,25 @@ def test_parse_errors_report_offsets():
             L.stats_close(h)
 
 
+def test_unaligned_device_chunks():
+    # chunks that start at arbitrary byte offsets of one device buffer
+    L = lib()
+    n = 20_000
+    txt = datagen.table1_csv(23, n)
+    d = _text_dev(txt)
+    h = L.stats_open(_cfg(L))
+    try:
+        pos, step = 0, 77_777
+        while pos < len(txt):
+            m = min(step, len(txt) - pos)
+            pos += L.stats_accumulate_text(h, d.data_ptr() + pos, m, is_last=(pos + m == len(txt)))
+        raw = L.stats_raw(h, 10)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(datagen.table1_aos(23, n)), TABLE1_INT)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+
+
 def test_incomplete_last_line_is_carried():
     L = lib()
     h = L.stats_open(_cfg(L, p=2, int_cols=[True, True]))
