@@ -234,9 +234,19 @@ __device__ inline double shift_of(const char* p) {
   return __longlong_as_double((long long)uniform64((uint64_t)__double_as_longlong(v)));
 }
 
-// All columns FP64 at consecutive offsets of a 16-byte aligned row.
+// All columns FP64 at consecutive offsets of a 16-byte aligned row whose
+// stride is 8p rounded up to a multiple of 16.  Row-major records put one row's values 8p bytes
+// apart, so lanes that each fetch their own row would scatter every load over
+// 64 rows.  Instead the workgroup stages a tile of TR rows, a contiguous byte
+// range, with 16-byte loads in address order (fully coalesced), keeping the
+// next tile in registers while it reduces the current one from LDS; each lane
+// then reads its RPI rows from LDS.
 template <int P, int RPI>
 __global__ __launch_bounds__(kThreads, (P <= 12 ? 2 : 1)) void k_aos_f64(Args a) {
+  constexpr int TR = kThreads * RPI;        // rows per tile
+  constexpr int SMAX = (8 * P + 15) / 16 * 16;  // the row stride (checked on the host)
+  constexpr int MAXB = TR * SMAX;            // staged bytes per tile
+  __shared__ __attribute__((aligned(16))) unsigned char s_tile[MAXB];
   const int64_t r0 = (int64_t)blockIdx.x * a.R;
   const int64_t r1 = min(r0 + a.R, a.nrows);
   const char* base = a.colbase[0];
@@ -252,28 +262,36 @@ __global__ __launch_bounds__(kThreads, (P <= 12 ? 2 : 1)) void k_aos_f64(Args a)
   A.zero();
   uint32_t bad = 0;
   const bool chk = a.chkmask != 0;
-  constexpr int NV = P / 2;  // 16-byte loads per row
-  int64_t r = r0 + (int64_t)threadIdx.x * RPI;
-  for (; r + RPI <= r1; r += (int64_t)kThreads * RPI) {
-    v2d raw[RPI][NV > 0 ? NV : 1];
-    double tail[RPI];
+  const int chunks = (int)(TR * stride / 16);       // 16-byte pieces per full tile
+  constexpr int MAXC = MAXB / 16 / kThreads;        // pieces per thread (bound)
+  const int myc = (chunks + kThreads - 1) / kThreads;
+  typedef unsigned int v4u __attribute__((ext_vector_type(4)));
+  v4u buf[MAXC];
+  const int64_t nfull = (r1 - r0) / TR;  // whole tiles
+  auto fetch = [&](int64_t tile) {
+    const v4u* src = (const v4u*)(base + (r0 + tile * TR) * stride);
 #pragma unroll
-    for (int k = 0; k < RPI; ++k) {
-      const double* row = (const double*)(base + (r + k) * stride);
-#pragma unroll
-      for (int v = 0; v < NV; ++v) raw[k][v] = __builtin_nontemporal_load((const v2d*)(row + 2 * v));
-      if (P & 1) tail[k] = __builtin_nontemporal_load(row + (P - 1));
+    for (int k = 0; k < MAXC; ++k) {
+      const int c = threadIdx.x + k * kThreads;
+      if (k < myc && c < chunks) buf[k] = __builtin_nontemporal_load(src + c);
     }
-    __builtin_amdgcn_sched_barrier(0);  // every load of the step is in flight before any use
+  };
+  if (nfull > 0) fetch(0);
+  for (int64_t tile = 0; tile < nfull; ++tile) {
+    __syncthreads();  // previous tile fully consumed
+#pragma unroll
+    for (int k = 0; k < MAXC; ++k) {
+      const int c = threadIdx.x + k * kThreads;
+      if (k < myc && c < chunks) *(v4u*)(s_tile + 16 * c) = buf[k];
+    }
+    __syncthreads();
+    if (tile + 1 < nfull) fetch(tile + 1);  // in flight while this tile is reduced
 #pragma unroll
     for (int k = 0; k < RPI; ++k) {
+      const double* row = (const double*)(s_tile + (threadIdx.x + k * kThreads) * stride);
       double d[P];
 #pragma unroll
-      for (int v = 0; v < NV; ++v) {
-        d[2 * v] = raw[k][v].x - K[2 * v];
-        d[2 * v + 1] = raw[k][v].y - K[2 * v + 1];
-      }
-      if (P & 1) d[P - 1] = tail[k] - K[P - 1];
+      for (int c = 0; c < P; ++c) d[c] = row[c] - K[c];
       if (chk) {
 #pragma unroll
         for (int c = 0; c < P; ++c)
@@ -282,8 +300,8 @@ __global__ __launch_bounds__(kThreads, (P <= 12 ? 2 : 1)) void k_aos_f64(Args a)
       A.add(d);
     }
   }
-  // ragged end of the block: at most RPI - 1 rows for this lane
-  for (; r < r1; ++r) {
+  // rows after the last whole tile
+  for (int64_t r = r0 + nfull * TR + threadIdx.x; r < r1; r += kThreads) {
     double d[P];
     generic_row<P>(a, r, K, Ki, d, bad);
     A.add(d);

@@ -269,7 +269,7 @@ extern "C" void stats_close(stats_ctx* h) {
   if (h->stream) (void)hipStreamSynchronize(h->stream);
   if (h->copy_stream) (void)hipStreamSynchronize(h->copy_stream);
   collect_timings(h);
-  void* bufs[] = {h->state[0], h->state[1], h->intf_dev, h->status_dev, h->rec, h->l1,
+  void* bufs[] = {h->state[0], h->state[1], h->intf_dev, h->status_dev, h->rec,
                   h->fin_out, h->fin_scratch, h->sel_dev, h->raw_out, h->stage_dev[0],
                   h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev};
   for (void* b : bufs)
@@ -307,7 +307,8 @@ static int layout_kind(const stats_ctx* h, const void* const* planes) {
   if (aos) {
     const int pl = h->cols[0].plane;
     const uintptr_t base = (uintptr_t)planes[pl] + (uintptr_t)h->cols[0].byte_offset;
-    if (base % 16 == 0 && h->row_stride[pl] % 16 == 0) return 1;
+    // the staged-tile kernel expects the row stride 8p rounded up to 16 bytes
+    if (base % 16 == 0 && h->row_stride[pl] == (8 * p + 15) / 16 * 16) return 1;
   }
   // Dense planes: each column alone in its plane with stride = element size.
   bool dense = true;
@@ -356,9 +357,6 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
     const int64_t nblocks = (rows + R - 1) / R;
     int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
     if (rc) return rc;
-    const int64_t l1_groups = (nblocks + 31) / 32;
-    rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
-    if (rc) return rc;
     AccumLaunch b = a;
     for (int c = 0; c < p; ++c) b.colbase[c] = a.colbase[c] + done * a.colstride[c];
     b.nrows = rows;
@@ -375,8 +373,7 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
-      launch_merge_records(h->rec, nblocks, p, a.intmask, h->intf_dev, h->l1, l1_groups,
-                           h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
       t.end();
     }
     e = hipGetLastError();

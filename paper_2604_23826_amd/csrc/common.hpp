@@ -303,8 +303,7 @@ struct AccumLaunch {
 int64_t launch_accum_small_p(const AccumLaunch& a, hipStream_t s);
 
 // Merge nblocks records into the state: cur -> next (double-buffered).
-void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, uint32_t intmask_lo,
-                          const uint8_t* intflags_dev, uint64_t* l1_scratch, int64_t l1_groups,
+void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intflags_dev,
                           const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s);
 
 // Merge two states: out = merge(a, b).

@@ -16,10 +16,11 @@
 //    This never subtracts X^T X and n mu mu^T (section "Numerical
 //    Considerations").
 //
-// One thread owns one entry (a column i, or a pair i <= j) and walks the
-// partial results in a fixed order, so the result is deterministic.  The
-// column means needed by a pair are recomputed by the pair's own thread with
-// the same operations as the column's thread, hence bitwise equal.
+// Each entry (a column i, or a pair i <= j) is owned by one workgroup or
+// thread that walks the partial results in a fixed order, so the result is
+// deterministic.  The column means needed by a pair are recomputed by the
+// pair's owner with the same operations as the column's owner, hence
+// bitwise equal.
 #include "common.hpp"
 
 namespace st {
@@ -62,70 +63,6 @@ __device__ inline double kval(uint64_t w, bool is_int) {
   return is_int ? (double)(int64_t)w : __longlong_as_double((long long)w);
 }
 
-// Level 1: records [g*G, min((g+1)*G, nblocks)) -> one partial state per g.
-__global__ __launch_bounds__(kThreads) void k_merge_l1(const uint64_t* __restrict__ rec,
-                                                       int64_t nblocks, int64_t G, int p,
-                                                       const uint8_t* __restrict__ intf,
-                                                       uint64_t* __restrict__ part,
-                                                       DevStatus* status) {
-  const Layout L = Layout::make(p);
-  const int64_t E = p + L.T;
-  const int64_t e = (int64_t)blockIdx.x * kThreads + threadIdx.x;
-  const int64_t g = blockIdx.y;
-  if (e >= E) return;
-  int i, j;
-  bool is_col;
-  entry_cols(p, e, &i, &j, &is_col);
-  const bool ii = intf[i], ij = intf[j];
-  const int64_t W = rec_words(p);
-  const int64_t b0 = g * G, b1 = min(b0 + G, nblocks);
-  Chan acc = {0.0, 0.0, 0.0, 0.0};
-  i128 exact = 0;
-  int64_t ntot = 0;
-  uint32_t inexact = 0;
-  const int64_t t = is_col ? tri(p, i, i) : e - p;
-  for (int64_t b = b0; b < b1; ++b) {
-    const uint64_t* r = rec + b * W;
-    const int64_t nb = (int64_t)r[0];
-    if (nb == 0) continue;
-    const double nbd = (double)nb;
-    const uint64_t Kiw = r[2 + i], Kjw = r[2 + j];
-    const double Si = __longlong_as_double((long long)r[2 + p + i]);
-    const double Sj = __longlong_as_double((long long)r[2 + p + j]);
-    const double Qij = __longlong_as_double((long long)r[2 + 2 * p + t]);
-    Chan blk;
-    blk.n = nbd;
-    blk.mi = kval(Kiw, ii) + Si / nbd;
-    blk.mj = kval(Kjw, ij) + Sj / nbd;
-    blk.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
-    chan_add(acc, blk);
-    ntot += nb;
-    if (is_col && ii) {
-      const int64_t K = (int64_t)Kiw;
-      const double Qii = __longlong_as_double((long long)r[2 + 2 * p + tri(p, i, i)]);
-      if (r[1] != 0 || !(Qii < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
-      exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
-    } else if (!is_col && ii && ij) {
-      const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
-      exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
-    }
-  }
-  uint64_t* o = part + g * L.words;
-  if (e == 0) {
-    o[0] = (uint64_t)ntot;
-    o[1] = 0;
-  }
-  if (is_col) {
-    store_i128(o + L.off_s + 2 * i, exact);
-    o[L.off_mu + i] = (uint64_t)__double_as_longlong(acc.mi);
-    // (the diagonal co-moment M2_ii is written by the pair thread (i, i))
-  } else {
-    store_i128(o + L.off_C + 2 * t, exact);
-    o[L.off_M2 + t] = (uint64_t)__double_as_longlong(acc.m2);
-  }
-  if (inexact) atomicOr(&status->bits, ST_INEXACT);
-}
-
 __device__ inline Chan chan_of(const uint64_t* s, const Layout& L, int i, int j, int64_t t) {
   Chan c;
   c.n = (double)(int64_t)s[0];
@@ -135,7 +72,7 @@ __device__ inline Chan chan_of(const uint64_t* s, const Layout& L, int i, int j,
   return c;
 }
 
-// Level 2: next = cur followed by parts[0..nparts) in order.
+// State merge: next = cur followed by parts[0..nparts) in order.
 __global__ __launch_bounds__(kThreads) void k_merge_l2(const uint64_t* __restrict__ cur,
                                                        const uint64_t* __restrict__ parts,
                                                        int64_t nparts, int p,
@@ -173,20 +110,111 @@ __global__ __launch_bounds__(kThreads) void k_merge_l2(const uint64_t* __restric
   }
 }
 
+// Records -> state in one pass: one workgroup per entry.  Thread t folds
+// blocks t, t + 256, ... in order, then the 256 partial results are combined
+// by a fixed binary tree in LDS (Chan update + exact 128-bit sums) and the
+// total is merged into the current state (cur -> next).  The tree shape is
+// fixed, so the result is deterministic.
+constexpr int kTreeThreads = 256;
+
+__global__ __launch_bounds__(kTreeThreads) void k_merge_tree(const uint64_t* __restrict__ rec,
+                                                             int64_t nblocks, int p,
+                                                             const uint8_t* __restrict__ intf,
+                                                             const uint64_t* __restrict__ cur,
+                                                             uint64_t* __restrict__ next,
+                                                             DevStatus* status) {
+  __shared__ double s_n[kTreeThreads], s_mi[kTreeThreads], s_mj[kTreeThreads], s_m2[kTreeThreads];
+  __shared__ uint64_t s_lo[kTreeThreads], s_hi[kTreeThreads];
+  const Layout L = Layout::make(p);
+  const int64_t e = blockIdx.x;
+  int i, j;
+  bool is_col;
+  entry_cols(p, e, &i, &j, &is_col);
+  const bool ii = intf[i], ij = intf[j];
+  const int64_t W = rec_words(p);
+  const int64_t t = is_col ? tri(p, i, i) : e - p;
+  Chan acc = {0.0, 0.0, 0.0, 0.0};
+  i128 exact = 0;
+  uint32_t inexact = 0;
+  for (int64_t b = threadIdx.x; b < nblocks; b += kTreeThreads) {
+    const uint64_t* r = rec + b * W;
+    const int64_t nb = (int64_t)r[0];
+    if (nb == 0) continue;
+    const double nbd = (double)nb;
+    const uint64_t Kiw = r[2 + i], Kjw = r[2 + j];
+    const double Si = __longlong_as_double((long long)r[2 + p + i]);
+    const double Sj = __longlong_as_double((long long)r[2 + p + j]);
+    const double Qij = __longlong_as_double((long long)r[2 + 2 * p + t]);
+    Chan blk;
+    blk.n = nbd;
+    blk.mi = kval(Kiw, ii) + Si / nbd;
+    blk.mj = kval(Kjw, ij) + Sj / nbd;
+    blk.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
+    chan_add(acc, blk);
+    if (is_col && ii) {
+      const int64_t K = (int64_t)Kiw;
+      if (r[1] != 0 || !(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
+      exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
+    } else if (!is_col && ii && ij) {
+      const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
+      exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
+    }
+  }
+  if (inexact) atomicOr(&status->bits, ST_INEXACT);
+  const int tid = threadIdx.x;
+  s_n[tid] = acc.n;
+  s_mi[tid] = acc.mi;
+  s_mj[tid] = acc.mj;
+  s_m2[tid] = acc.m2;
+  s_lo[tid] = (uint64_t)(u128)exact;
+  s_hi[tid] = (uint64_t)((u128)exact >> 64);
+  __syncthreads();
+  for (int s = kTreeThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      Chan a = {s_n[tid], s_mi[tid], s_mj[tid], s_m2[tid]};
+      const Chan b = {s_n[tid + s], s_mi[tid + s], s_mj[tid + s], s_m2[tid + s]};
+      chan_add(a, b);
+      s_n[tid] = a.n;
+      s_mi[tid] = a.mi;
+      s_mj[tid] = a.mj;
+      s_m2[tid] = a.m2;
+      const uint64_t w0[2] = {s_lo[tid], s_hi[tid]}, w1[2] = {s_lo[tid + s], s_hi[tid + s]};
+      const i128 sum = load_i128(w0) + load_i128(w1);
+      s_lo[tid] = (uint64_t)(u128)sum;
+      s_hi[tid] = (uint64_t)((u128)sum >> 64);
+    }
+    __syncthreads();
+  }
+  if (tid == 0) {
+    const int64_t tt = is_col ? -1 : t;
+    Chan tot = chan_of(cur, L, i, j, tt);
+    const Chan add = {s_n[0], s_mi[0], s_mj[0], s_m2[0]};
+    chan_add(tot, add);
+    const uint64_t w[2] = {s_lo[0], s_hi[0]};
+    const i128 add_exact = load_i128(w);
+    if (is_col) {
+      store_i128(next + L.off_s + 2 * i, load_i128(cur + L.off_s + 2 * i) + add_exact);
+      next[L.off_mu + i] = (uint64_t)__double_as_longlong(tot.mi);
+      if (e == 0) {
+        next[0] = (uint64_t)((int64_t)cur[0] + (int64_t)s_n[0]);
+        next[1] = 0;
+      }
+    } else {
+      const i128 base = load_i128(cur + L.off_C + 2 * t);
+      store_i128(next + L.off_C + 2 * t, (ii && ij) ? base + add_exact : base);
+      next[L.off_M2 + t] = (uint64_t)__double_as_longlong(tot.m2);
+    }
+  }
+}
+
 }  // namespace
 
-void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, uint32_t /*intmask_lo*/,
-                          const uint8_t* intf, uint64_t* l1, int64_t l1_groups,
+void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intf,
                           const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s) {
   const Layout L = Layout::make(p);
   const int64_t E = p + L.T;
-  const int64_t G = (nblocks + l1_groups - 1) / l1_groups;
-  const int64_t groups = (nblocks + G - 1) / G;
-  dim3 grid1((unsigned)((E + kThreads - 1) / kThreads), (unsigned)groups);
-  hipLaunchKernelGGL(k_merge_l1, grid1, dim3(kThreads), 0, s, rec, nblocks, G, p, intf, l1,
-                     status);
-  dim3 grid2((unsigned)((E + kThreads - 1) / kThreads));
-  hipLaunchKernelGGL(k_merge_l2, grid2, dim3(kThreads), 0, s, cur, l1, groups, p, intf, next);
+  hipLaunchKernelGGL(k_merge_tree, dim3((unsigned)E), dim3(kTreeThreads), 0, s, rec, nblocks, p,
+                     intf, cur, next, status);
 }
 
 void launch_merge_states(const uint64_t* a, const uint64_t* b, uint64_t* out, int p,

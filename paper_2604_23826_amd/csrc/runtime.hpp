@@ -32,8 +32,6 @@ struct stats_ctx {
   // scratch
   uint64_t* rec = nullptr;
   size_t rec_cap = 0;
-  uint64_t* l1 = nullptr;
-  size_t l1_cap = 0;
   double* fin_out = nullptr;
   size_t fin_out_cap = 0;
   double* fin_scratch = nullptr;

@@ -29,7 +29,7 @@ namespace st {
 namespace text {
 
 constexpr int kThreads = 256;
-constexpr int SEG = 1 << 16;     // bytes of line starts per workgroup
+constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
 constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = 256;       // bytes of line starts per thread
 constexpr int STAGE = 16 + SEG + MAXLINE;
@@ -69,187 +69,215 @@ __device__ inline U256 u256_mul_small(U256 a, uint32_t m) {
   return r;
 }
 
-// Decimal text [b, e) -> nearest FP64.  Returns false on malformed input or
-// a value outside the supported range.  The first 38 significant digits are
-// kept exactly (128 bits); any further nonzero digit is kept as a sticky
-// digit 1 appended to them, which places the value strictly between two
-// 38-digit neighbours and rounds like the full expansion whenever no FP64
-// rounding midpoint lies that close (always, e.g., for printed doubles).
-__device__ inline bool parse_decimal(const Stage& S, int64_t b, int64_t e, double* out) {
-  int64_t i = b;
-  bool neg = false;
-  int c = S.at(i);
-  if (c == '-' || c == '+') {
-    neg = c == '-';
-    ++i;
+// Correctly rounded value of (w + sticky) * 2^e2 where w has 54..128 bits
+// and sticky marks a nonzero remainder below the last bit of w.
+__device__ inline double round_to_double(u128 w, bool sticky, int e2, bool neg) {
+  int bl = 0;
+  for (u128 t = w; t; t >>= 1) ++bl;
+  const int extra = bl - 53;
+  uint64_t m;
+  if (extra > 0) {
+    const u128 low = w & (((u128)1 << extra) - 1);
+    const u128 half = (u128)1 << (extra - 1);
+    m = (uint64_t)(w >> extra);
+    if (low > half || (low == half && (sticky || (m & 1)))) ++m;
+    e2 += extra;
+  } else {
+    m = (uint64_t)w << (-extra);
+    e2 += extra;
   }
-  u128 w = 0;
-  int nd = 0;
-  int64_t q = 0;
-  bool digits = false, sticky = false;
-  for (; i < e; ++i) {
-    c = S.at(i);
-    if (c < '0' || c > '9') break;
-    digits = true;
-    const int d = c - '0';
-    if (w == 0 && d == 0) continue;
-    if (nd < 38) {
-      w = w * 10 + (u128)d;
-      ++nd;
-    } else {
-      sticky |= d != 0;
-      ++q;
-    }
+  if (m == ((uint64_t)1 << 53)) {
+    m >>= 1;
+    ++e2;
   }
-  if (i < e && S.at(i) == '.') {
-    for (++i; i < e; ++i) {
-      c = S.at(i);
-      if (c < '0' || c > '9') break;
-      digits = true;
-      const int d = c - '0';
-      if (w == 0 && d == 0) {
-        --q;
-        continue;
-      }
-      if (nd < 38) {
-        w = w * 10 + (u128)d;
-        ++nd;
-        --q;
-      } else {
-        sticky |= d != 0;
-      }
-    }
+  const double r = ldexp((double)m, e2);
+  return neg ? -r : r;
+}
+
+__device__ inline uint64_t pow5_u64(int k) {  // 5^k for k <= 27
+  uint64_t r = 1;
+  for (int i = 0; i < k; ++i) r *= 5;
+  return r;
+}
+
+// Exact w * 10^q for w < 2^64 and |q| <= 27: w 5^q fits 128 bits for q > 0;
+// for q < 0 the quotient w 2^k / 5^-q (k chosen for 54..56 bits) comes from
+// an FP64 estimate corrected with the exact 128-bit remainder.
+__device__ inline double fast_decimal(uint64_t w, int q, bool neg) {
+  if (q >= 0) return round_to_double((u128)w * pow5_u64(q), false, q, neg);
+  const uint64_t D = pow5_u64(-q);
+  int bw = 0, bd = 0;
+  for (uint64_t t = w; t; t >>= 1) ++bw;
+  for (uint64_t t = D; t; t >>= 1) ++bd;
+  const int k = 55 - bw + bd;  // w 2^k has 55 + bd <= 119 bits
+  const u128 N = (u128)w << k;
+  const double est = (double)N / (double)D;
+  uint64_t Q = (uint64_t)est;  // within a few units of floor(N / D)
+  __int128 rem = (__int128)N - (__int128)((u128)Q * D);
+  while (rem < 0) {
+    --Q;
+    rem += D;
   }
-  if (!digits) return false;
-  if (i < e && (S.at(i) == 'e' || S.at(i) == 'E')) {
-    ++i;
-    bool eneg = false;
-    c = S.at(i);
-    if (c == '-' || c == '+') {
-      eneg = c == '-';
-      ++i;
-    }
-    int64_t ex = 0;
-    bool ed = false;
-    for (; i < e; ++i) {
-      c = S.at(i);
-      if (c < '0' || c > '9') break;
-      ed = true;
-      if (ex < 100000) ex = ex * 10 + (c - '0');
-    }
-    if (!ed) return false;
-    q += eneg ? -ex : ex;
+  while (rem >= (__int128)D) {
+    ++Q;
+    rem -= D;
   }
-  if (i != e) return false;
-  if (w == 0) {
-    *out = neg ? -0.0 : 0.0;
-    return true;
-  }
+  return round_to_double((u128)Q, rem != 0, -k + q, neg);
+}
+
+// Exact ratio path for everything else (more than 19 digits, |q| up to 57).
+__device__ __attribute__((noinline)) double slow_decimal(u128 w, int q, bool sticky, bool neg) {
   U256 num = u256_from_u128(w), den = u256_from_u128((u128)1);
   if (sticky) {
     num = u256_mul_small(num, 10u);
     num.w[0] |= 1u;  // (10 w + 1) 10^(q - 1); the low digit was 0
     --q;
   }
-  // range: the exact ratio must fit the 256-bit division
-  const int lw = u256_bitlen(num);
-  if (q >= 0) {
-    if (lw + (q * 3402 + 1023) / 1024 > 250) return false;  // log2(10) < 3402/1024
+  if (q >= 0)
     for (int k = 0; k < q; ++k) num = u256_mul_small(num, 10u);
-  } else {
-    if (-q > 57) return false;
+  else
     for (int k = 0; k < -q; ++k) den = u256_mul_small(den, 10u);
-  }
-  *out = u256_div_to_double(neg, num, den);
-  return true;
+  return u256_div_to_double(neg, num, den);
 }
 
-// Decimal integer text [b, e) (at most 18 digits).
-__device__ inline bool parse_integer(const Stage& S, int64_t b, int64_t e, int64_t* out) {
-  int64_t i = b;
+// Parses one field starting at f; on success returns the position of the
+// terminating byte (',' or '\n' or nend) and the value bits in *bits (int64
+// for integer columns, FP64 otherwise).  Returns -1 - pos on malformed input.
+// Decimal text keeps 38 significant digits exactly plus a sticky digit for
+// any further nonzero digit, which rounds like the full expansion whenever no
+// FP64 rounding midpoint lies within 1e-38 relative (always, e.g., for
+// printed doubles).
+__device__ inline int64_t parse_field(const Stage& S, int64_t f, int64_t nend, bool is_int,
+                                      uint64_t* bits) {
+  int64_t i = f;
+  int c = i < nend ? S.at(i) : -1;
   bool neg = false;
-  int c = S.at(i);
   if (c == '-' || c == '+') {
     neg = c == '-';
     ++i;
+    c = i < nend ? S.at(i) : -1;
   }
-  if (i >= e) return false;
-  int64_t v = 0;
+  u128 w = 0;
   int nd = 0;
-  for (; i < e; ++i) {
-    c = S.at(i);
-    if (c < '0' || c > '9') return false;
-    if (++nd > 18) return false;
-    v = v * 10 + (c - '0');
+  int q = 0;
+  bool digits = false, sticky = false, bad = false;
+  while (c >= '0' && c <= '9') {
+    digits = true;
+    const int d = c - '0';
+    if (w != 0 || d != 0) {
+      if (nd < 38) {
+        w = w * 10 + (u128)d;
+        ++nd;
+      } else {
+        sticky |= d != 0;
+        ++q;
+      }
+    }
+    ++i;
+    c = i < nend ? S.at(i) : -1;
   }
-  *out = neg ? -v : v;
-  return true;
+  if (is_int) {
+    if (!digits || nd > 18 || q != 0) return -1 - i;
+    if (c != ',' && c != '\n' && c != -1) return -1 - i;
+    const int64_t v = (int64_t)(uint64_t)w;
+    *bits = (uint64_t)(neg ? -v : v);
+    return i;
+  }
+  if (c == '.') {
+    ++i;
+    c = i < nend ? S.at(i) : -1;
+    while (c >= '0' && c <= '9') {
+      digits = true;
+      const int d = c - '0';
+      if (w == 0 && d == 0) {
+        --q;
+      } else if (nd < 38) {
+        w = w * 10 + (u128)d;
+        ++nd;
+        --q;
+      } else {
+        sticky |= d != 0;
+      }
+      ++i;
+      c = i < nend ? S.at(i) : -1;
+    }
+  }
+  if (!digits) return -1 - i;
+  if (c == 'e' || c == 'E') {
+    ++i;
+    c = i < nend ? S.at(i) : -1;
+    bool eneg = false;
+    if (c == '-' || c == '+') {
+      eneg = c == '-';
+      ++i;
+      c = i < nend ? S.at(i) : -1;
+    }
+    int ex = 0;
+    bool ed = false;
+    while (c >= '0' && c <= '9') {
+      ed = true;
+      if (ex < 100000) ex = ex * 10 + (c - '0');
+      ++i;
+      c = i < nend ? S.at(i) : -1;
+    }
+    if (!ed) return -1 - i;
+    q += eneg ? -ex : ex;
+  }
+  if (c != ',' && c != '\n' && c != -1) return -1 - i;
+  double v;
+  if (w == 0) {
+    v = neg ? -0.0 : 0.0;
+  } else if (!sticky && nd <= 19 && q >= -27 && q <= 27) {
+    v = fast_decimal((uint64_t)w, q, neg);
+  } else {
+    // range of the exact ratio: 256-bit numerator and denominator
+    int lw = 0;
+    for (u128 t = w; t; t >>= 1) ++lw;
+    const int qq = sticky ? q - 1 : q;
+    if (qq > 0 && lw + 4 + (qq * 3402 + 1023) / 1024 > 250) bad = true;  // log2(10) < 3402/1024
+    if (qq < -57) bad = true;
+    if (bad) return -1 - f;
+    v = slow_decimal(w, q, sticky, neg);
+  }
+  (void)bad;
+  *bits = (uint64_t)__double_as_longlong(v);
+  return i;
 }
 
-// Parses the line starting at L (p fields).  Returns the end position (the
-// '\n' or nend), or -1 on a malformed line (*bad_at = offending field).
-template <int P>
-__device__ inline int64_t parse_line(const Args& a, const Stage& S, int64_t L, double (&x)[P],
-                                     int64_t (&xi)[P], int64_t* bad_at) {
-  int64_t f0 = L;
-  bool ok = true;
-#pragma unroll
-  for (int c = 0; c < P; ++c) {
-    int64_t f1 = f0;
-    int ch = S.at(f1);
-    while (ch >= 0 && ch != ',' && ch != '\n' && f1 < a.nend) {
-      ++f1;
-      ch = S.at(f1);
-    }
-    const bool last = (c == P - 1);
-    const bool term_ok = last ? (ch == '\n' || f1 >= a.nend) : (ch == ',');
-    if (ch < 0 && f1 < a.nend) {  // ran past the staged bytes: line too long
-      *bad_at = f0;
-      return -1;
-    }
-    if (ok) {
-      if (!term_ok || f1 == f0) {
-        ok = false;
-        *bad_at = f0;
-      } else if ((a.intmask >> c) & 1u) {
-        int64_t v;
-        if (parse_integer(S, f0, f1, &v)) {
-          xi[c] = v;
-          x[c] = (double)v;
-        } else {
-          ok = false;
-          *bad_at = f0;
-        }
-      } else {
-        double v;
-        if (parse_decimal(S, f0, f1, &v)) {
-          x[c] = v;
-          xi[c] = 0;
-        } else {
-          ok = false;
-          *bad_at = f0;
-        }
-      }
-    }
+// Parses the line starting at L (p fields) into row[0..p).  Returns the
+// position of its end ('\n' or nend), or -1 - end on a malformed line
+// (*bad_at = the offending field's offset).
+__device__ inline int64_t parse_line(const Args& a, const Stage& S, int64_t L, uint64_t* row,
+                                     int64_t* bad_at) {
+  int64_t f = L;
+  for (int c = 0; c < a.p; ++c) {
+    uint64_t bits = 0;
+    const int64_t r = parse_field(S, f, a.nend, (a.intmask >> c) & 1u, &bits);
+    const bool last = c == a.p - 1;
+    int term = r >= 0 ? (r < a.nend ? S.at(r) : -1) : 0;
+    const bool ok = r >= 0 && (last ? (term == '\n' || r >= a.nend) : term == ',');
     if (!ok) {
-      // skip to the end of the line
-      while (ch >= 0 && ch != '\n' && f1 < a.nend) {
-        ++f1;
-        ch = S.at(f1);
+      *bad_at = f;
+      int64_t e = r >= 0 ? r : -1 - r;  // skip to the end of the line
+      while (e < a.nend) {
+        const int ch = S.at(e);
+        if (ch == '\n' || ch < 0) break;
+        ++e;
       }
-      return -1 - f1;  // encoded end for the caller's scan (always < -1)
+      return -1 - e;
     }
-    f0 = f1 + 1;
-    if (last) return f1;
+    row[c] = bits;
+    if (last) return r;
+    f = r + 1;
   }
-  return f0;
+  return f;
 }
 
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   __shared__ unsigned char s_buf[STAGE_PADDED];
-  __shared__ double sK[P];
-  __shared__ int64_t sKi[P];
+  __shared__ uint64_t s_row[kThreads][P];
+  __shared__ uint64_t sKb[P];
   __shared__ unsigned long long s_n;
   const int64_t s0 = (int64_t)blockIdx.x * SEG;
   const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
@@ -264,8 +292,8 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
     const int head = (int)(alo - lo);
     const int nvec = (int)((ahi - alo) / 16);
     for (int v = threadIdx.x; v < nvec; v += kThreads) {
-      const uint4 q = *(const uint4*)(alo + 16 * (uintptr_t)v);
-      const unsigned char* qb = (const unsigned char*)&q;
+      const uint4 qv = *(const uint4*)(alo + 16 * (uintptr_t)v);
+      const unsigned char* qb = (const unsigned char*)&qv;
 #pragma unroll
       for (int k = 0; k < 16; ++k) s_buf[pad(head + 16 * v + k)] = qb[k];
     }
@@ -279,34 +307,26 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   __syncthreads();
   const Stage S{s_buf, w0, n};
 
-  // block shift: the first line starting in [s0, s1)
+  // block shift: the first line starting in [s0, s1) (zeros if none parses)
   if (threadIdx.x == 0) {
     int64_t L = s0;
     if (s0 > 0) {
       while (L < s1 && S.at(L - 1) != '\n') ++L;
     }
-    double x[P];
-    int64_t xi[P];
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      x[c] = 0.0;
-      xi[c] = 0;
-    }
+    for (int c = 0; c < P; ++c) s_row[0][c] = 0;
     int64_t bad_at;
-    if (L < s1) (void)parse_line<P>(a, S, L, x, xi, &bad_at);
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      sK[c] = ((a.intmask >> c) & 1u) ? (double)xi[c] : x[c];
-      sKi[c] = xi[c];
-    }
+    if (L >= s1 || parse_line(a, S, L, s_row[0], &bad_at) < 0)
+      for (int c = 0; c < P; ++c) s_row[0][c] = 0;
+    for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
   }
   __syncthreads();
   double K[P];
   int64_t Ki[P];
 #pragma unroll
   for (int c = 0; c < P; ++c) {
-    K[c] = sK[c];
-    Ki[c] = sKi[c];
+    const bool ic = (a.intmask >> c) & 1u;
+    Ki[c] = ic ? (int64_t)sKb[c] : 0;
+    K[c] = ic ? (double)Ki[c] : __longlong_as_double((long long)sKb[c]);
   }
 
   acc::Acc<P> A;
@@ -316,27 +336,29 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   int64_t first_bad = INT64_MAX;
   const int64_t t0 = s0 + (int64_t)threadIdx.x * SLICE;
   const int64_t t1 = min(t0 + SLICE, s1);
+  uint64_t* row = s_row[threadIdx.x];
   int64_t L = t0;
   while (L < t1) {
     if (L > 0 && S.at(L - 1) != '\n') {
       ++L;
       continue;
     }
-    double x[P];
-    int64_t xi[P];
     int64_t bad_at = INT64_MAX;
-    const int64_t end = parse_line<P>(a, S, L, x, xi, &bad_at);
+    const int64_t end = parse_line(a, S, L, row, &bad_at);
     if (end >= 0) {
       double d[P];
 #pragma unroll
-      for (int c = 0; c < P; ++c)
-        d[c] = ((a.intmask >> c) & 1u) ? (double)(xi[c] - Ki[c]) : x[c] - K[c];
+      for (int c = 0; c < P; ++c) {
+        const uint64_t b = row[c];
+        d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - Ki[c])
+                                        : __longlong_as_double((long long)b) - K[c];
+      }
       A.add(d);
       ++nrows;
       L = end + 1;
     } else {
       first_bad = min(first_bad, bad_at);
-      L = (end < -1) ? (-1 - end) + 1 : L + 1;
+      L = (-1 - end) + 1;
     }
   }
   if (first_bad != INT64_MAX) {
@@ -349,7 +371,7 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
 }
 
 // Position after the last '\n' in [0, n), or 0 when there is none; one
-// workgroup scans backwards in 64 KB windows.
+// workgroup scans backwards in SEG-byte windows.
 __global__ void k_last_newline(const char* buf, int64_t n, int64_t* out) {
   __shared__ unsigned long long best;
   if (threadIdx.x == 0) best = 0;
@@ -381,9 +403,6 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   const int64_t W = rec_words(p);
   const Layout L = Layout::make(p);
   int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
-  if (rc) return rc;
-  const int64_t l1_groups = (nblocks + 31) / 32;
-  rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
   if (rc) return rc;
   Args a;
   memset(&a, 0, sizeof a);
@@ -426,8 +445,7 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   {
     Timer t;
     t.begin(h, STATS_K_MERGE);
-    launch_merge_records(h->rec, nblocks, p, intmask, h->intf_dev, h->l1, l1_groups,
-                         h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+    launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
     t.end();
   }
   err = hipGetLastError();

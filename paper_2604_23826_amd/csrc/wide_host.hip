@@ -67,9 +67,6 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
     if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
     rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
     if (rc) return rc;
-    const int64_t l1_groups = (nblocks + 31) / 32;
-    rc = ensure_dev(h, (void**)&h->l1, &h->l1_cap, (size_t)(l1_groups * L.words * 8));
-    if (rc) return rc;
     wide::Args a;
     a.slots = slots_dev;
     a.p = p;
@@ -91,7 +88,7 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
-      launch_merge_records(h->rec, nblocks, p, 0, h->intf_dev, h->l1, l1_groups, h->state[h->cur],
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur],
                            h->state[h->cur ^ 1], h->status_dev, h->stream);
       t.end();
     }
