@@ -36,7 +36,9 @@ HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
 FP64_PEAK_TFLOPS = 78.6
 PMC_FILE = os.path.join(ROOT, "profiles", "accum_small_p_table1_2e9_pmc.json")
-KERNEL_SRC = os.path.join(ROOT, "paper_2604_23826_amd", "csrc", "accum_impl.hpp")
+# sources of the narrow-table planes kernel whose counters are on file
+KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_23826_amd", "csrc", f)
+               for f in ("accum_common.hpp", "accum_planes.hpp")]
 
 
 def log(*a):
@@ -44,8 +46,11 @@ def log(*a):
 
 
 def kernel_sha():
-    with open(KERNEL_SRC, "rb") as f:
-        return hashlib.sha256(f.read()).hexdigest()[:16]
+    h = hashlib.sha256()
+    for p in KERNEL_SRCS:
+        with open(p, "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()[:16]
 
 
 def traffic_from_profile(rows_per_launch):
@@ -455,7 +460,7 @@ def main():
     ap.add_argument("--rows", type=int, default=None)
     ap.add_argument("--chunk-rows", type=int, default=1 << 28)
     ap.add_argument("--wave-rows", type=int, default=600_000_000)
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 24)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 26)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-staged", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")

@@ -22,7 +22,7 @@
 // the handle (STATS_E_PARSE, smallest byte offset) and its row is skipped.
 #include <cstring>
 
-#include "accum_impl.hpp"
+#include "accum_common.hpp"
 #include "runtime.hpp"
 
 namespace st {
