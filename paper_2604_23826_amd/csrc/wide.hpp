@@ -46,7 +46,39 @@ struct SegArgs {
   unsigned long long* counter;        // work queue head (device word)
 };
 
+// FP32 matrix on BF16 matrix cores (wide_syrk.hip): F vector columns at
+// consecutive 4-byte offsets of one plane, up to kSyrkMaxExtra other columns.
+constexpr int kSyrkGroup = 128;
+constexpr int kSyrkMaxExtra = 2;
+constexpr int kSyrkMaxPairs = 36;  // F <= 1024: at most 8 groups
+
+struct SyrkExtra {
+  const char* base;  // element of row 0 of the launch
+  int64_t stride;
+  int32_t kind;      // STATS_*
+  uint8_t chk;       // FP column flagged INTEGER: check values
+  uint8_t isint;     // integer column: shift stored as an integer
+  uint8_t pad[2];
+};
+
+struct SyrkArgs {
+  const char* xbase;        // vector column 0 in row 0 of the launch (16-byte aligned)
+  int64_t xstride;          // row stride in bytes (multiple of 16)
+  int F;                    // vector columns (multiple of 4), slots 0..F-1
+  int ne;                   // extra columns, slots F..F+ne-1
+  SyrkExtra ex[kSyrkMaxExtra];
+  int npairs;
+  int2 pairs[kSyrkMaxPairs];  // (A, B) group pairs, A <= B
+  int p;                    // F + ne
+  const int32_t* col_of;    // user column of each slot (device)
+  int64_t nblocks, nrows, R;  // R: rows per block (multiple of 64)
+  uint64_t* rec;
+  DevStatus* status;
+};
+
 }  // namespace wide
+
+void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s);
 
 // Persistent segmented launch (zeroes the queue first): nwg workgroups.
 void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s);
