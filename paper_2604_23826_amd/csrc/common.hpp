@@ -145,18 +145,21 @@ __host__ __device__ inline bool u256_is_zero(const U256& a) {
 }
 
 __host__ __device__ inline int u256_bitlen(const U256& a) {
-  for (int k = 3; k >= 0; --k) {
-    if (a.w[k]) {
-      uint64_t v = a.w[k];
-      int b = 0;
-      while (v) {
-        v >>= 1;
-        ++b;
-      }
-      return 64 * k + b;
-    }
-  }
+  for (int k = 3; k >= 0; --k)
+    if (a.w[k]) return 64 * k + 64 - __builtin_clzll(a.w[k]);
   return 0;
+}
+
+// a * m for m < 2^64 (the product must fit in 256 bits).
+__host__ __device__ inline U256 u256_mul64(const U256& a, uint64_t m) {
+  U256 r;
+  u128 carry = 0;
+  for (int k = 0; k < 4; ++k) {
+    const u128 t = (u128)a.w[k] * m + carry;
+    r.w[k] = (uint64_t)t;
+    carry = t >> 64;
+  }
+  return r;
 }
 
 __host__ __device__ inline U256 u256_shl(const U256& a, int s) {
@@ -181,8 +184,8 @@ __host__ __device__ inline U256 u256_shr1(const U256& a) {
 
 // Correctly rounded (to nearest, ties to even) value of (neg ? -1 : 1) * a / b
 // for b > 0 and a < 2^190.  Exact long division of the top 65 quotient bits
-// plus a sticky remainder bit.
-__host__ __device__ inline double u256_div_to_double(bool neg, U256 a, U256 b) {
+// plus a sticky remainder bit (the general case of u256_div_to_double).
+__host__ __device__ inline double u256_div_long(bool neg, U256 a, U256 b) {
   if (u256_is_zero(a)) return 0.0;
   const int la = u256_bitlen(a), lb = u256_bitlen(b);
   int k = 64 - (la - lb);  // quotient of (a * 2^k) / b has 64 or 65 bits
@@ -225,6 +228,90 @@ __host__ __device__ inline double u256_div_to_double(bool neg, U256 a, U256 b) {
   }
   double r = ldexp((double)m, e);
   return neg ? -r : r;
+}
+
+// a * 2^(1 - e) compared with t * b (t odd): the sign of a / b - (t / 2) 2^e.
+__host__ __device__ inline int u256_cmp_half(const U256& a, const U256& b, int e, uint64_t t) {
+  U256 x = a, y = u256_mul64(b, t);
+  if (1 - e >= 0) x = u256_shl(a, 1 - e);
+  else y = u256_shl(y, e - 1);
+  return u256_cmp(x, y);
+}
+
+// Top 64 bits of a (bit length la > 0) times 2^(la - 64), as a double.
+__host__ __device__ inline double u256_approx(const U256& a, int la) {
+  if (la <= 64) return (double)a.w[0];
+  const int sh = la - 64, q = sh >> 6, r = sh & 63;
+  uint64_t v = a.w[q] >> r;
+  if (r && q + 1 < 4) v |= a.w[q + 1] << (64 - r);
+  return ldexp((double)v, sh);
+}
+
+// Correctly rounded (to nearest, ties to even) value of (neg ? -1 : 1) * a / b
+// for b > 0, a < 2^190, b < 2^190.  A double quotient of the leading bits is
+// within a few units in the last place; its mantissa m is then moved to the
+// right neighbour by exact comparisons of a / b with the midpoints
+// (m +- 1/2) 2^e, and a tie goes to the even mantissa.  Quotients outside the
+// normal range, or an estimate that does not settle, take the long division.
+__host__ __device__ inline double u256_div_to_double(bool neg, U256 a, U256 b) {
+  if (u256_is_zero(a)) return 0.0;
+  const int la = u256_bitlen(a), lb = u256_bitlen(b);
+  if (la > 190 || lb > 190) return u256_div_long(neg, a, b);
+  const double q0 = u256_approx(a, la) / u256_approx(b, lb);
+  int E;
+  const double f = frexp(q0, &E);  // q0 = f 2^E, f in [1/2, 1)
+  if (!(E > -1000 && E < 1000)) return u256_div_long(neg, a, b);
+  int64_t m = (int64_t)ldexp(f, 53);  // [2^52, 2^53)
+  int e = E - 53;
+  const int64_t lo = (int64_t)1 << 52, hi = (int64_t)1 << 53;
+  for (int it = 0; it < 8; ++it) {
+    const int up = u256_cmp_half(a, b, e, (uint64_t)(2 * m + 1));
+    if (up > 0) {  // a/b above the upper midpoint
+      ++m;
+      if (m == hi) {
+        m = lo;
+        ++e;
+      }
+      continue;
+    }
+    if (up == 0) {  // exactly halfway to m + 1
+      if (m & 1) ++m;
+      if (m == hi) {
+        m = lo;
+        ++e;
+      }
+      const double r = ldexp((double)m, e);
+      return neg ? -r : r;
+    }
+    // below the upper midpoint; the lower midpoint of m = 2^52 sits at a
+    // quarter unit (the binade below has half the spacing)
+    const int dn = m == lo ? u256_cmp_half(a, b, e - 1, (uint64_t)(4 * m - 1))
+                           : u256_cmp_half(a, b, e, (uint64_t)(2 * m - 1));
+    if (dn < 0) {
+      if (m == lo) {
+        m = hi - 1;
+        --e;
+      } else {
+        --m;
+      }
+      continue;
+    }
+    if (dn == 0) {  // exactly halfway to the lower neighbour
+      if (m & 1) {
+        if (m == lo) {
+          m = hi - 1;
+          --e;
+        } else {
+          --m;
+        }
+      }
+      const double r = ldexp((double)m, e);
+      return neg ? -r : r;
+    }
+    const double r = ldexp((double)m, e);
+    return neg ? -r : r;
+  }
+  return u256_div_long(neg, a, b);
 }
 
 // (neg, |v|) of a signed 128-bit value.

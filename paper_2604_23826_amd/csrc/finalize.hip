@@ -14,14 +14,19 @@
 // Table 3: eigenvalues descending, variance %, cumulative %, loadings (one
 // row per component).
 //
-// One workgroup does the whole job; the matrices live in a global scratch
-// buffer (they stay in L2).
+// One workgroup does the whole job.  The working matrices live in LDS when
+// they fit (q <= kLdsQ, every PCA of the narrow path), else in a global
+// scratch buffer that stays in L2; there each thread loads the 2 x 2 blocks
+// of several rotations before it writes any (the blocks of one round are
+// disjoint), so the L2 latency is paid once per batch.
 #include "common.hpp"
 
 namespace st {
 namespace {
 
 constexpr int kThreads = 1024;
+constexpr int kLdsQ = 60;  // A and V in LDS up to this size (2 q^2 doubles <= 57.6 KiB)
+constexpr int kNB = 4;     // 2 x 2 blocks per thread and batch (global-memory case)
 
 struct Args {
   const uint64_t* state;
@@ -34,6 +39,7 @@ struct Args {
   int want_vectors;
   double* out;
   double* scratch;
+  int lds_mat;  // A and V in dynamic LDS after the rotation tables
 };
 
 // Round-robin schedule on m (even) players: player at position pos in round r.
@@ -47,6 +53,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   const int64_t n = (int64_t)st[0];
   const int q = f.q;
   const int tid = threadIdx.x;
+  const int nth = blockDim.x;  // 64 .. kThreads, chosen by the launcher from q
   double* mean = f.out;
   double* cov = mean + q;
   double* corr = cov + (int64_t)q * q;
@@ -54,8 +61,6 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   double* evec = ev + q;
   double* varp = evec + (int64_t)q * q;
   double* cump = varp + q;
-  double* A = f.scratch;
-  double* V = A + (int64_t)q * q;
 
   __shared__ int s_flag;
   __shared__ int s_rot;
@@ -68,15 +73,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   double* rapq = rt + npairs;
   int* pp = (int*)(rapq + npairs);
   int* pq = pp + npairs;
+  double* A = f.scratch;
+  if (f.lds_mat) A = s_dyn + 4 * npairs + (npairs + 1) / 2 * 2;  // after pp, pq (8-byte aligned)
+  double* V = A + (int64_t)q * q;
 
   // ---- means and covariance ----
   const double dn = (double)(n - f.ddof);
-  for (int a = tid; a < q; a += kThreads) {
+  for (int a = tid; a < q; a += nth) {
     const int i = f.sel[a];
     mean[a] = f.intf[i] ? exact_mean(st, L, i, n)
                         : __longlong_as_double((long long)st[L.off_mu + i]);
   }
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
     const int a = (int)(idx / q), b = (int)(idx % q);
     if (a > b) continue;
     const int i = f.sel[a], j = f.sel[b];  // sel ascending, so i <= j
@@ -88,7 +96,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   }
   __syncthreads();
   // ---- correlation ----
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
     const int a = (int)(idx / q), b = (int)(idx % q);
     const double caa = cov[(int64_t)a * q + a], cbb = cov[(int64_t)b * q + b];
     double v;
@@ -102,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   // ---- PCA input ----
   const double* M = f.pca_on ? cov : corr;
   int bad = 0;
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) {
+  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
     const double v = M[idx];
     if (!isfinite(v)) bad = 1;
     A[idx] = v;
@@ -111,8 +119,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   if (bad) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
-    for (int64_t idx = tid; idx < (int64_t)q * q; idx += kThreads) evec[idx] = __builtin_nan("");
-    for (int a = tid; a < q; a += kThreads) {
+    for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) evec[idx] = __builtin_nan("");
+    for (int a = tid; a < q; a += nth) {
       ev[a] = varp[a] = cump[a] = __builtin_nan("");
     }
     return;
@@ -125,7 +133,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     __syncthreads();
     for (int r = 0; r < m - 1; ++r) {
       // rotations of this round (one thread per disjoint pair)
-      for (int k = tid; k < npairs; k += kThreads) {
+      for (int k = tid; k < npairs; k += nth) {
         int a = rr_player(k, r, m), b = rr_player(m - 1 - k, r, m);
         if (a > b) {
           const int x = a;
@@ -154,37 +162,56 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
         rapq[k] = apq;
       }
       __syncthreads();
-      // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns)
-      for (int64_t idx = tid; idx < (int64_t)npairs * npairs; idx += kThreads) {
-        const int u = (int)(idx / npairs), v = (int)(idx % npairs);
-        const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
-        const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
-        if (su == 0.0 && sv == 0.0) continue;
-        const bool bq = b < q, dq = d2 < q;
-        double x00 = A[(int64_t)a * q + c2];
-        double x01 = dq ? A[(int64_t)a * q + d2] : 0.0;
-        double x10 = bq ? A[(int64_t)b * q + c2] : 0.0;
-        double x11 = (bq && dq) ? A[(int64_t)b * q + d2] : 0.0;
-        // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
-        const double y00 = cu * x00 - su * x10, y10 = su * x00 + cu * x10;
-        const double y01 = cu * x01 - su * x11, y11 = su * x01 + cu * x11;
-        // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
-        double z00 = cv * y00 - sv * y01, z01 = sv * y00 + cv * y01;
-        double z10 = cv * y10 - sv * y11, z11 = sv * y10 + cv * y11;
-        if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
-          const double t = rt[u], apq = rapq[u];
-          z00 = A[(int64_t)a * q + a] - t * apq;
-          z11 = A[(int64_t)b * q + b] + t * apq;
-          z01 = 0.0;
-          z10 = 0.0;
+      // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns); the blocks
+      // of a round are disjoint, so a batch is loaded before it is written
+      const int64_t nblk = (int64_t)npairs * npairs;
+      for (int64_t base = tid; base < nblk; base += (int64_t)nth * kNB) {
+        double x[kNB][4];
+#pragma unroll
+        for (int e = 0; e < kNB; ++e) {
+          const int64_t idx = base + (int64_t)e * nth;
+          x[e][0] = x[e][1] = x[e][2] = x[e][3] = 0.0;
+          if (idx >= nblk) continue;
+          const int u = (int)(idx / npairs), v = (int)(idx % npairs);
+          if (rs[u] == 0.0 && rs[v] == 0.0) continue;
+          const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
+          const bool bq = b < q, dq = d2 < q;
+          x[e][0] = A[(int64_t)a * q + c2];
+          if (dq) x[e][1] = A[(int64_t)a * q + d2];
+          if (bq) x[e][2] = A[(int64_t)b * q + c2];
+          if (bq && dq) x[e][3] = A[(int64_t)b * q + d2];
         }
-        A[(int64_t)a * q + c2] = z00;
-        if (dq) A[(int64_t)a * q + d2] = z01;
-        if (bq) A[(int64_t)b * q + c2] = z10;
-        if (bq && dq) A[(int64_t)b * q + d2] = z11;
+#pragma unroll
+        for (int e = 0; e < kNB; ++e) {
+          const int64_t idx = base + (int64_t)e * nth;
+          if (idx >= nblk) continue;
+          const int u = (int)(idx / npairs), v = (int)(idx % npairs);
+          const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
+          if (su == 0.0 && sv == 0.0) continue;
+          const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
+          const bool bq = b < q, dq = d2 < q;
+          const double x00 = x[e][0], x01 = x[e][1], x10 = x[e][2], x11 = x[e][3];
+          // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
+          const double y00 = cu * x00 - su * x10, y10 = su * x00 + cu * x10;
+          const double y01 = cu * x01 - su * x11, y11 = su * x01 + cu * x11;
+          // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
+          double z00 = cv * y00 - sv * y01, z01 = sv * y00 + cv * y01;
+          double z10 = cv * y10 - sv * y11, z11 = sv * y10 + cv * y11;
+          if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
+            const double t = rt[u], apq = rapq[u];
+            z00 = x00 - t * apq;
+            z11 = x11 + t * apq;
+            z01 = 0.0;
+            z10 = 0.0;
+          }
+          A[(int64_t)a * q + c2] = z00;
+          if (dq) A[(int64_t)a * q + d2] = z01;
+          if (bq) A[(int64_t)b * q + c2] = z10;
+          if (bq && dq) A[(int64_t)b * q + d2] = z11;
+        }
       }
       // V <- V J
-      for (int64_t idx = tid; idx < (int64_t)q * npairs; idx += kThreads) {
+      for (int64_t idx = tid; idx < (int64_t)q * npairs; idx += nth) {
         const int row = (int)(idx / npairs), u = (int)(idx % npairs);
         const double s = rs[u];
         if (s == 0.0) continue;
@@ -201,7 +228,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   }
 
   // ---- sort descending (ties: lower index first), sign rule, percentages ----
-  for (int k = tid; k < q; k += kThreads) {
+  for (int k = tid; k < q; k += nth) {
     const double lk = A[(int64_t)k * q + k];
     int rank = 0;
     for (int j = 0; j < q; ++j) {
@@ -292,8 +319,13 @@ void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
   a.out = F.out;
   a.scratch = F.scratch;
   const int npairs = (F.q + (F.q & 1)) / 2;
-  const size_t shm = (size_t)npairs * (4 * sizeof(double) + 2 * sizeof(int));
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), shm, s, a);
+  size_t shm = (size_t)npairs * 4 * sizeof(double) + (size_t)(npairs + 1) / 2 * 2 * sizeof(double);
+  a.lds_mat = F.q <= kLdsQ;
+  if (a.lds_mat) shm += 2 * sizeof(double) * (size_t)F.q * F.q;
+  // one wave for the small matrices of the narrow path (its barriers cost
+  // nothing), more threads for wide ones
+  const int nth = F.q <= 16 ? 64 : F.q <= kLdsQ ? 256 : kThreads;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(nth), shm, s, a);
 }
 
 void launch_raw(const uint64_t* state, int p, const uint8_t* intf, double* out, hipStream_t s) {
