@@ -61,6 +61,7 @@ struct stats_ctx {
   hipGraphExec_t graph_exec = nullptr;
   hipStream_t cap_stream = nullptr;
   int graph_nwg = 0;
+  int graph_aos64 = -1;  // kernel captured in the graph: 1 = k_seg_aos64
   int64_t seg_tile_rows = 0;
   int seg_wg_per_cu = 0;
   int64_t seg_cap_rt = 0;

@@ -307,6 +307,26 @@ static int seg_prepare(stats_ctx* h, const void* const* planes, int ST, int64_t 
   return STATS_OK;
 }
 
+// FP64 records of 256 bytes with column c at byte 8c (p <= 32), 16-byte
+// aligned: the layout of k_seg_aos64.
+static bool seg_aos64_layout(const stats_ctx* h, const void* const* planes) {
+  if (h->p > 32) return false;
+  const int pl = h->cols[0].plane;
+  if (h->row_stride[pl] != 256 || ((uintptr_t)planes[pl] & 15u) != 0) return false;
+  for (int c = 0; c < h->p; ++c) {
+    const stats_column& col = h->cols[c];
+    if (col.plane != pl || col.dtype != STATS_F64 || col.byte_offset != 8 * c) return false;
+  }
+  return true;
+}
+
+static void seg_launch(const stats_ctx* h, bool aos64, const wide::Args& a, const wide::SegArgs& g,
+                       int ST, int nwg, hipStream_t s) {
+  (void)h;
+  if (aos64) launch_seg_aos64(a, g, nwg, s);
+  else launch_seg(a, g, ST, nwg, s);
+}
+
 static int num_cus(int device) {
   int n = 0;
   if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0)
@@ -318,6 +338,7 @@ static int num_cus(int device) {
 // each candidate tile height and occupancy; keeps the fastest per row.
 static int autotune(stats_ctx* h, const void* const* planes, const int64_t* off, int ST,
                     const std::vector<int2>& sts, Tuned* best) {
+  const bool aos64 = seg_aos64_layout(h, planes);
   const int64_t cands_T[] = {8192, 16384, 32768, 65536, 131072};
   const int cands_W[] = {2, 4, 8};
   const int64_t sample_rows = (int64_t)1 << 26;
@@ -360,9 +381,9 @@ static int autotune(stats_ctx* h, const void* const* planes, const int64_t* off,
     a.status = h->status_dev;
     wide::SegArgs s{B.rowtiles, B.nrt, B.counter};
     for (int W : cands_W) {
-      launch_seg(a, s, ST, ncu * W, h->stream);  // warm
+      seg_launch(h, aos64, a, s, ST, ncu * W, h->stream);  // warm
       (void)hipEventRecord(e0, h->stream);
-      launch_seg(a, s, ST, ncu * W, h->stream);
+      seg_launch(h, aos64, a, s, ST, ncu * W, h->stream);
       (void)hipEventRecord(e1, h->stream);
       e = hipEventSynchronize(e1);
       if (e != hipSuccess) {
@@ -482,6 +503,7 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
   a.status = h->status_dev;
   wide::SegArgs sa{B.rowtiles, B.nrt, B.counter};
   const int nwg = num_cus(h->device) * tu.wg_per_cu;
+  const bool aos64 = seg_aos64_layout(h, planes);
 
   if (!h->graph_exec) {
     // capture on a private stream (the handle's stream may be a legacy default stream)
@@ -491,7 +513,7 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
     }
     e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
-    launch_seg(a, sa, ST, nwg, h->cap_stream);
+    seg_launch(h, aos64, a, sa, ST, nwg, h->cap_stream);
     const size_t shm = sizeof(double) * (size_t)(p + 1);
     hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)h->ngroups), dim3(kMergeThreads), shm,
                        h->cap_stream, h->rec, B.gt, p, h->intf_dev, h->state[0], h->status_dev);
@@ -500,8 +522,9 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
     e = hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0);
     if (e != hipSuccess) return hip_fail(h, e, "hipGraphInstantiate");
     h->graph_nwg = nwg;
+    h->graph_aos64 = (int)aos64;
   }
-  if (h->graph_nwg != nwg) {
+  if (h->graph_nwg != nwg || h->graph_aos64 != (int)aos64) {
     (void)hipGraphExecDestroy(h->graph_exec);
     (void)hipGraphDestroy(h->graph);
     h->graph_exec = nullptr;

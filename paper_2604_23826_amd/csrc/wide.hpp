@@ -82,6 +82,8 @@ void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s);
 
 // Persistent segmented launch (zeroes the queue first): nwg workgroups.
 void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s);
+// The same for FP64 records of 256 bytes, column c at byte 8c, p <= 32.
+void launch_seg_aos64(const wide::Args& a, const wide::SegArgs& g, int nwg, hipStream_t s);
 
 // st = super-group width (32 or 64); mode = MODE_FP64 or MODE_SPLIT.
 void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s);
