@@ -9,8 +9,8 @@
 // Work split: workgroup w owns the lines whose first byte lies in
 // [w * SEG, (w + 1) * SEG); within it, thread t owns the lines starting in its
 // 256-byte slice.  The workgroup stages its bytes (plus MAXLINE bytes of the
-// next segment, for lines that run past the end) in LDS with 4 bytes of
-// padding per 256 so that threads reading their own slices hit different
+// next segment, for lines that run past the end) in LDS with 16 bytes of
+// padding per 256, so that threads reading their own slices hit different
 // banks.  The block shift is the workgroup's first line.
 //
 // Fields: integer columns are decimal integers (optional sign, at most 18
@@ -33,7 +33,7 @@ constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
 constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = 256;       // bytes of line starts per thread
 constexpr int STAGE = 16 + SEG + MAXLINE;
-constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 1) * 4;
+constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 1) * 16;
 
 struct Args {
   const char* buf;
@@ -46,17 +46,35 @@ struct Args {
   DevStatus* status;
 };
 
-__device__ inline int pad(int i) { return i + ((i >> 8) << 2); }
+__device__ inline int pad(int i) { return i + ((i >> 8) << 4); }
 
+
+// Staged text [w0, w0 + n); positions at or past lim (= min(nend, w0 + n))
+// read as -1.
 struct Stage {
   const unsigned char* s;
-  int64_t w0;  // stream offset of staged byte 0
-  int n;       // staged bytes
+  int64_t w0;   // stream offset of staged byte 0
+  int n;        // staged bytes
+  int64_t lim;  // first position that is not text of this chunk
+};
+
+// A thread's reader of the staged text (one LDS byte per character; the
+// staged bytes are padded 16 per 256 so that threads reading their own slices
+// fall on different banks).
+struct Cur {
+  const Stage* S;
+  __device__ explicit Cur(const Stage& st) : S(&st) {}
   __device__ inline int at(int64_t pos) const {
-    const int64_t i = pos - w0;
-    return (i >= 0 && i < n) ? s[pad((int)i)] : -1;
+    if (pos >= S->lim) return -1;
+    return ((const __attribute__((address_space(3))) unsigned char*)S->s)[pad((int)(pos - S->w0))];
   }
 };
+
+__device__ inline int bitlen64(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
+__device__ inline int bitlen128(u128 v) {
+  const uint64_t hi = (uint64_t)(v >> 64);
+  return hi ? 128 - __builtin_clzll(hi) : bitlen64((uint64_t)v);
+}
 
 __device__ inline U256 u256_mul_small(U256 a, uint32_t m) {
   U256 r;
@@ -72,8 +90,7 @@ __device__ inline U256 u256_mul_small(U256 a, uint32_t m) {
 // Correctly rounded value of (w + sticky) * 2^e2 where w has 54..128 bits
 // and sticky marks a nonzero remainder below the last bit of w.
 __device__ inline double round_to_double(u128 w, bool sticky, int e2, bool neg) {
-  int bl = 0;
-  for (u128 t = w; t; t >>= 1) ++bl;
+  const int bl = bitlen128(w);
   const int extra = bl - 53;
   uint64_t m;
   if (extra > 0) {
@@ -106,9 +123,7 @@ __device__ inline uint64_t pow5_u64(int k) {  // 5^k for k <= 27
 __device__ inline double fast_decimal(uint64_t w, int q, bool neg) {
   if (q >= 0) return round_to_double((u128)w * pow5_u64(q), false, q, neg);
   const uint64_t D = pow5_u64(-q);
-  int bw = 0, bd = 0;
-  for (uint64_t t = w; t; t >>= 1) ++bw;
-  for (uint64_t t = D; t; t >>= 1) ++bd;
+  const int bw = bitlen64(w), bd = bitlen64(D);
   const int k = 55 - bw + bd;  // w 2^k has 55 + bd <= 119 bits
   const u128 N = (u128)w << k;
   const double est = (double)N / (double)D;
@@ -146,21 +161,121 @@ __device__ __attribute__((noinline)) double slow_decimal(u128 w, int q, bool sti
 // Decimal text keeps 38 significant digits exactly plus a sticky digit for
 // any further nonzero digit, which rounds like the full expansion whenever no
 // FP64 rounding midpoint lies within 1e-38 relative (always, e.g., for
-// printed doubles).
-__device__ inline int64_t parse_field(const Stage& S, int64_t f, int64_t nend, bool is_int,
-                                      uint64_t* bits) {
+// printed doubles).  Significands of up to 19 digits (every integer field and
+// printed double) are gathered in 64 bits; longer ones go through
+// parse_wide.
+struct Parsed {
+  int64_t pos;    // terminating byte, or -1 - pos on malformed input
+  uint64_t bits;  // value
+};
+__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int64_t f, bool is_int);
+
+__device__ inline double decimal_value(u128 w, int nd, int q, bool sticky, bool neg, bool* bad) {
+  if (w == 0) return neg ? -0.0 : 0.0;
+  if (!sticky && nd <= 19 && q >= -27 && q <= 27) return fast_decimal((uint64_t)w, q, neg);
+  // range of the exact ratio: 256-bit numerator and denominator
+  const int lw = bitlen128(w);
+  const int qq = sticky ? q - 1 : q;
+  if (qq > 0 && lw + 4 + (qq * 3402 + 1023) / 1024 > 250) *bad = true;  // log2(10) < 3402/1024
+  if (qq < -57) *bad = true;
+  if (*bad) return 0.0;
+  return slow_decimal(w, q, sticky, neg);
+}
+
+__device__ inline int64_t parse_field(Cur& C, int64_t f, bool is_int, uint64_t* bits) {
   int64_t i = f;
-  int c = i < nend ? S.at(i) : -1;
+  int c = C.at(i);
   bool neg = false;
   if (c == '-' || c == '+') {
     neg = c == '-';
-    ++i;
-    c = i < nend ? S.at(i) : -1;
+    c = C.at(++i);
+  }
+  uint64_t w = 0;
+  int nd = 0;
+  int q = 0;
+  bool digits = false;
+  while (c >= '0' && c <= '9') {
+    digits = true;
+    const int d = c - '0';
+    if (w != 0 || d != 0) {
+      if (nd == 19) {
+        const Parsed r = parse_wide(*C.S, f, is_int);
+        *bits = r.bits;
+        return r.pos;
+      }
+      w = w * 10 + (uint64_t)d;
+      ++nd;
+    }
+    c = C.at(++i);
+  }
+  if (is_int) {
+    if (!digits || nd > 18) return -1 - i;
+    if (c != ',' && c != '\n' && c != -1) return -1 - i;
+    const int64_t v = (int64_t)w;
+    *bits = (uint64_t)(neg ? -v : v);
+    return i;
+  }
+  if (c == '.') {
+    c = C.at(++i);
+    while (c >= '0' && c <= '9') {
+      digits = true;
+      const int d = c - '0';
+      if (w == 0 && d == 0) {
+        --q;
+      } else {
+        if (nd == 19) {
+          const Parsed r = parse_wide(*C.S, f, is_int);
+          *bits = r.bits;
+          return r.pos;
+        }
+        w = w * 10 + (uint64_t)d;
+        ++nd;
+        --q;
+      }
+      c = C.at(++i);
+    }
+  }
+  if (!digits) return -1 - i;
+  if (c == 'e' || c == 'E') {
+    c = C.at(++i);
+    bool eneg = false;
+    if (c == '-' || c == '+') {
+      eneg = c == '-';
+      c = C.at(++i);
+    }
+    int ex = 0;
+    bool ed = false;
+    while (c >= '0' && c <= '9') {
+      ed = true;
+      if (ex < 100000) ex = ex * 10 + (c - '0');
+      c = C.at(++i);
+    }
+    if (!ed) return -1 - i;
+    q += eneg ? -ex : ex;
+  }
+  if (c != ',' && c != '\n' && c != -1) return -1 - i;
+  bool bad = false;
+  const double v = decimal_value((u128)w, nd, q, false, neg, &bad);
+  if (bad) return -1 - f;
+  *bits = (uint64_t)__double_as_longlong(v);
+  return i;
+}
+
+// The same for significands of more than 19 digits: 128-bit accumulation.
+__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int64_t f, bool is_int) {
+  Cur C(S);
+  Parsed out{0, 0};
+  int64_t i = f;
+  int c = C.at(i);
+  bool neg = false;
+  if (c == '-' || c == '+') {
+    neg = c == '-';
+    c = C.at(++i);
   }
   u128 w = 0;
   int nd = 0;
   int q = 0;
-  bool digits = false, sticky = false, bad = false;
+  bool digits = false, sticky = false;
   while (c >= '0' && c <= '9') {
     digits = true;
     const int d = c - '0';
@@ -173,19 +288,11 @@ __device__ inline int64_t parse_field(const Stage& S, int64_t f, int64_t nend, b
         ++q;
       }
     }
-    ++i;
-    c = i < nend ? S.at(i) : -1;
+    c = C.at(++i);
   }
-  if (is_int) {
-    if (!digits || nd > 18 || q != 0) return -1 - i;
-    if (c != ',' && c != '\n' && c != -1) return -1 - i;
-    const int64_t v = (int64_t)(uint64_t)w;
-    *bits = (uint64_t)(neg ? -v : v);
-    return i;
-  }
+  if (is_int) return Parsed{-1 - i, 0};  // more than 18 digits
   if (c == '.') {
-    ++i;
-    c = i < nend ? S.at(i) : -1;
+    c = C.at(++i);
     while (c >= '0' && c <= '9') {
       digits = true;
       const int d = c - '0';
@@ -198,69 +305,52 @@ __device__ inline int64_t parse_field(const Stage& S, int64_t f, int64_t nend, b
       } else {
         sticky |= d != 0;
       }
-      ++i;
-      c = i < nend ? S.at(i) : -1;
+      c = C.at(++i);
     }
   }
-  if (!digits) return -1 - i;
+  if (!digits) return Parsed{-1 - i, 0};
   if (c == 'e' || c == 'E') {
-    ++i;
-    c = i < nend ? S.at(i) : -1;
+    c = C.at(++i);
     bool eneg = false;
     if (c == '-' || c == '+') {
       eneg = c == '-';
-      ++i;
-      c = i < nend ? S.at(i) : -1;
+      c = C.at(++i);
     }
     int ex = 0;
     bool ed = false;
     while (c >= '0' && c <= '9') {
       ed = true;
       if (ex < 100000) ex = ex * 10 + (c - '0');
-      ++i;
-      c = i < nend ? S.at(i) : -1;
+      c = C.at(++i);
     }
-    if (!ed) return -1 - i;
+    if (!ed) return Parsed{-1 - i, 0};
     q += eneg ? -ex : ex;
   }
-  if (c != ',' && c != '\n' && c != -1) return -1 - i;
-  double v;
-  if (w == 0) {
-    v = neg ? -0.0 : 0.0;
-  } else if (!sticky && nd <= 19 && q >= -27 && q <= 27) {
-    v = fast_decimal((uint64_t)w, q, neg);
-  } else {
-    // range of the exact ratio: 256-bit numerator and denominator
-    int lw = 0;
-    for (u128 t = w; t; t >>= 1) ++lw;
-    const int qq = sticky ? q - 1 : q;
-    if (qq > 0 && lw + 4 + (qq * 3402 + 1023) / 1024 > 250) bad = true;  // log2(10) < 3402/1024
-    if (qq < -57) bad = true;
-    if (bad) return -1 - f;
-    v = slow_decimal(w, q, sticky, neg);
-  }
-  (void)bad;
-  *bits = (uint64_t)__double_as_longlong(v);
-  return i;
+  if (c != ',' && c != '\n' && c != -1) return Parsed{-1 - i, 0};
+  bool bad = false;
+  const double v = decimal_value(w, nd, q, sticky, neg, &bad);
+  if (bad) return Parsed{-1 - f, 0};
+  out.pos = i;
+  out.bits = (uint64_t)__double_as_longlong(v);
+  return out;
 }
 
 // Parses the line starting at L (p fields) into row[0..p).  Returns the
 // position of its end ('\n' or nend), or -1 - end on a malformed line
 // (*bad_at = the offending field's offset).
-__device__ inline int64_t parse_line(const Args& a, const Stage& S, int64_t L, uint64_t* row,
-                                     int64_t* bad_at) {
+__device__ inline int64_t parse_line(const Args& a, Cur& C, int64_t L, uint64_t* row, int64_t* bad_at) {
   int64_t f = L;
   for (int c = 0; c < a.p; ++c) {
     uint64_t bits = 0;
-    const int64_t r = parse_field(S, f, a.nend, (a.intmask >> c) & 1u, &bits);
+    const int64_t r = parse_field(C, f, (a.intmask >> c) & 1u, &bits);
     const bool last = c == a.p - 1;
-    int term = r >= 0 ? (r < a.nend ? S.at(r) : -1) : 0;
-    const bool ok = r >= 0 && (last ? (term == '\n' || r >= a.nend) : term == ',');
+    const int term = r >= 0 ? C.at(r) : 0;
+    const bool ok = r >= 0 && (last ? (term == '\n' || term == -1) : term == ',');
     if (!ok) {
       *bad_at = f;
       int64_t e = r >= 0 ? r : -1 - r;  // skip to the end of the line
-      while (e < a.nend) {
-        const int ch = S.at(e);
+      for (;;) {
+        const int ch = C.at(e);
         if (ch == '\n' || ch < 0) break;
         ++e;
       }
@@ -274,7 +364,7 @@ __device__ inline int64_t parse_line(const Args& a, const Stage& S, int64_t L, u
 }
 
 template <int P>
-__global__ __launch_bounds__(kThreads) void k_text(Args a) {
+__global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   __shared__ unsigned char s_buf[STAGE_PADDED];
   __shared__ uint64_t s_row[kThreads][P];
   __shared__ uint64_t sKb[P];
@@ -305,29 +395,26 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   }
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  const Stage S{s_buf, w0, n};
+  const Stage S{s_buf, w0, n, min(a.nend, w0 + (int64_t)n)};
 
   // block shift: the first line starting in [s0, s1) (zeros if none parses)
   if (threadIdx.x == 0) {
+    Cur C0(S);
     int64_t L = s0;
     if (s0 > 0) {
-      while (L < s1 && S.at(L - 1) != '\n') ++L;
+      while (L < s1 && C0.at(L - 1) != '\n') ++L;
     }
     for (int c = 0; c < P; ++c) s_row[0][c] = 0;
     int64_t bad_at;
-    if (L >= s1 || parse_line(a, S, L, s_row[0], &bad_at) < 0)
+    if (L >= s1 || parse_line(a, C0, L, s_row[0], &bad_at) < 0)
       for (int c = 0; c < P; ++c) s_row[0][c] = 0;
     for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
   }
   __syncthreads();
-  double K[P];
-  int64_t Ki[P];
+  // shift words: int64 for integer columns, FP64 bits otherwise
+  uint64_t K64[P];
 #pragma unroll
-  for (int c = 0; c < P; ++c) {
-    const bool ic = (a.intmask >> c) & 1u;
-    Ki[c] = ic ? (int64_t)sKb[c] : 0;
-    K[c] = ic ? (double)Ki[c] : __longlong_as_double((long long)sKb[c]);
-  }
+  for (int c = 0; c < P; ++c) K64[c] = sKb[c];
 
   acc::Acc<P> A;
   A.zero();
@@ -338,20 +425,20 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   const int64_t t1 = min(t0 + SLICE, s1);
   uint64_t* row = s_row[threadIdx.x];
   int64_t L = t0;
+  Cur C(S);
+  // first line start at or after t0
+  if (L > 0)
+    while (L < t1 && C.at(L - 1) != '\n') ++L;
   while (L < t1) {
-    if (L > 0 && S.at(L - 1) != '\n') {
-      ++L;
-      continue;
-    }
     int64_t bad_at = INT64_MAX;
-    const int64_t end = parse_line(a, S, L, row, &bad_at);
+    const int64_t end = parse_line(a, C, L, row, &bad_at);
     if (end >= 0) {
       double d[P];
 #pragma unroll
       for (int c = 0; c < P; ++c) {
         const uint64_t b = row[c];
-        d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - Ki[c])
-                                        : __longlong_as_double((long long)b) - K[c];
+        d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
+                                        : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
       }
       A.add(d);
       ++nrows;
@@ -367,6 +454,14 @@ __global__ __launch_bounds__(kThreads) void k_text(Args a) {
   }
   atomicAdd(&s_n, nrows);
   __syncthreads();
+  double K[P];
+  int64_t Ki[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    const bool ic = (a.intmask >> c) & 1u;
+    Ki[c] = ic ? (int64_t)K64[c] : 0;
+    K[c] = ic ? (double)Ki[c] : __longlong_as_double((long long)K64[c]);
+  }
   acc::finish_block<P>(a.acc, A, K, Ki, bad, 0, (int64_t)s_n);
 }
 
