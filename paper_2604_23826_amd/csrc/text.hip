@@ -49,13 +49,14 @@ struct Args {
 __device__ inline int pad(int i) { return i + ((i >> 8) << 4); }
 
 
-// Staged text [w0, w0 + n); positions at or past lim (= min(nend, w0 + n))
+// Staged text [w0, w0 + n) of the chunk.  The parser works on positions
+// relative to w0 (32-bit); positions at or past lim (min(nend, w0 + n) - w0)
 // read as -1.
 struct Stage {
   const unsigned char* s;
-  int64_t w0;   // stream offset of staged byte 0
-  int n;        // staged bytes
-  int64_t lim;  // first position that is not text of this chunk
+  int64_t w0;  // stream offset of staged byte 0
+  int n;       // staged bytes
+  int lim;     // first relative position that is not text of this chunk
 };
 
 // A thread's reader of the staged text (one LDS byte per character; the
@@ -64,9 +65,9 @@ struct Stage {
 struct Cur {
   const Stage* S;
   __device__ explicit Cur(const Stage& st) : S(&st) {}
-  __device__ inline int at(int64_t pos) const {
+  __device__ inline int at(int pos) const {
     if (pos >= S->lim) return -1;
-    return ((const __attribute__((address_space(3))) unsigned char*)S->s)[pad((int)(pos - S->w0))];
+    return ((const __attribute__((address_space(3))) unsigned char*)S->s)[pad(pos)];
   }
 };
 
@@ -165,10 +166,10 @@ __device__ __attribute__((noinline)) double slow_decimal(u128 w, int q, bool sti
 // printed double) are gathered in 64 bits; longer ones go through
 // parse_wide.
 struct Parsed {
-  int64_t pos;    // terminating byte, or -1 - pos on malformed input
+  int pos;        // terminating byte, or -1 - pos on malformed input
   uint64_t bits;  // value
 };
-__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int64_t f, bool is_int);
+__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int f, bool is_int);
 
 __device__ inline double decimal_value(u128 w, int nd, int q, bool sticky, bool neg, bool* bad) {
   if (w == 0) return neg ? -0.0 : 0.0;
@@ -182,8 +183,8 @@ __device__ inline double decimal_value(u128 w, int nd, int q, bool sticky, bool 
   return slow_decimal(w, q, sticky, neg);
 }
 
-__device__ inline int64_t parse_field(Cur& C, int64_t f, bool is_int, uint64_t* bits) {
-  int64_t i = f;
+__device__ inline int parse_field(Cur& C, int f, bool is_int, uint64_t* bits) {
+  int i = f;
   int c = C.at(i);
   bool neg = false;
   if (c == '-' || c == '+') {
@@ -262,10 +263,10 @@ __device__ inline int64_t parse_field(Cur& C, int64_t f, bool is_int, uint64_t* 
 }
 
 // The same for significands of more than 19 digits: 128-bit accumulation.
-__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int64_t f, bool is_int) {
+__device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int f, bool is_int) {
   Cur C(S);
   Parsed out{0, 0};
-  int64_t i = f;
+  int i = f;
   int c = C.at(i);
   bool neg = false;
   if (c == '-' || c == '+') {
@@ -338,17 +339,17 @@ __device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int64_t f, bool 
 // Parses the line starting at L (p fields) into row[0..p).  Returns the
 // position of its end ('\n' or nend), or -1 - end on a malformed line
 // (*bad_at = the offending field's offset).
-__device__ inline int64_t parse_line(const Args& a, Cur& C, int64_t L, uint64_t* row, int64_t* bad_at) {
-  int64_t f = L;
+__device__ inline int parse_line(const Args& a, Cur& C, int L, uint64_t* row, int* bad_at) {
+  int f = L;
   for (int c = 0; c < a.p; ++c) {
     uint64_t bits = 0;
-    const int64_t r = parse_field(C, f, (a.intmask >> c) & 1u, &bits);
+    const int r = parse_field(C, f, (a.intmask >> c) & 1u, &bits);
     const bool last = c == a.p - 1;
     const int term = r >= 0 ? C.at(r) : 0;
     const bool ok = r >= 0 && (last ? (term == '\n' || term == -1) : term == ',');
     if (!ok) {
       *bad_at = f;
-      int64_t e = r >= 0 ? r : -1 - r;  // skip to the end of the line
+      int e = r >= 0 ? r : -1 - r;  // skip to the end of the line
       for (;;) {
         const int ch = C.at(e);
         if (ch == '\n' || ch < 0) break;
@@ -395,18 +396,19 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   }
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
-  const Stage S{s_buf, w0, n, min(a.nend, w0 + (int64_t)n)};
+  const Stage S{s_buf, w0, n, (int)(min(a.nend, w0 + (int64_t)n) - w0)};
+  const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);  // relative positions
 
   // block shift: the first line starting in [s0, s1) (zeros if none parses)
   if (threadIdx.x == 0) {
     Cur C0(S);
-    int64_t L = s0;
+    int L = s0r;
     if (s0 > 0) {
-      while (L < s1 && C0.at(L - 1) != '\n') ++L;
+      while (L < s1r && C0.at(L - 1) != '\n') ++L;
     }
     for (int c = 0; c < P; ++c) s_row[0][c] = 0;
-    int64_t bad_at;
-    if (L >= s1 || parse_line(a, C0, L, s_row[0], &bad_at) < 0)
+    int bad_at;
+    if (L >= s1r || parse_line(a, C0, L, s_row[0], &bad_at) < 0)
       for (int c = 0; c < P; ++c) s_row[0][c] = 0;
     for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
   }
@@ -420,18 +422,18 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   A.zero();
   uint32_t bad = 0;
   unsigned long long nrows = 0;
-  int64_t first_bad = INT64_MAX;
-  const int64_t t0 = s0 + (int64_t)threadIdx.x * SLICE;
-  const int64_t t1 = min(t0 + SLICE, s1);
+  int first_bad = INT32_MAX;
+  const int t0 = s0r + (int)threadIdx.x * SLICE;
+  const int t1 = min(t0 + SLICE, s1r);
   uint64_t* row = s_row[threadIdx.x];
-  int64_t L = t0;
+  int L = t0;
   Cur C(S);
   // first line start at or after t0
-  if (L > 0)
+  if (w0 + L > 0)
     while (L < t1 && C.at(L - 1) != '\n') ++L;
   while (L < t1) {
-    int64_t bad_at = INT64_MAX;
-    const int64_t end = parse_line(a, C, L, row, &bad_at);
+    int bad_at = INT32_MAX;
+    const int end = parse_line(a, C, L, row, &bad_at);
     if (end >= 0) {
       double d[P];
 #pragma unroll
@@ -448,8 +450,8 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
       L = (-1 - end) + 1;
     }
   }
-  if (first_bad != INT64_MAX) {
-    atomicMin(&a.status->parse_off, (unsigned long long)(a.base_off + first_bad));
+  if (first_bad != INT32_MAX) {
+    atomicMin(&a.status->parse_off, (unsigned long long)(a.base_off + w0 + first_bad));
     atomicOr(&a.status->bits, ST_PARSE);
   }
   atomicAdd(&s_n, nrows);
