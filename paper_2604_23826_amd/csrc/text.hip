@@ -32,6 +32,7 @@ constexpr int kThreads = 256;
 constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
 constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = 256;       // bytes of line starts per thread
+constexpr int MAXLS = 4096;      // line starts per workgroup kept in the table
 constexpr int STAGE = 16 + SEG + MAXLINE;
 constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 1) * 16;
 
@@ -370,6 +371,8 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   __shared__ uint64_t s_row[kThreads][P];
   __shared__ uint64_t sKb[P];
   __shared__ unsigned long long s_n;
+  __shared__ unsigned short s_ls[MAXLS];  // line starts (stage-relative)
+  __shared__ int s_wsum[kThreads / 64];
   const int64_t s0 = (int64_t)blockIdx.x * SEG;
   const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
   const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
@@ -423,15 +426,9 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   uint32_t bad = 0;
   unsigned long long nrows = 0;
   int first_bad = INT32_MAX;
-  const int t0 = s0r + (int)threadIdx.x * SLICE;
-  const int t1 = min(t0 + SLICE, s1r);
-  uint64_t* row = s_row[threadIdx.x];
-  int L = t0;
   Cur C(S);
-  // first line start at or after t0
-  if (w0 + L > 0)
-    while (L < t1 && C.at(L - 1) != '\n') ++L;
-  while (L < t1) {
+  auto take_line = [&](int L) -> int {  // parses and accumulates one line; returns the next position
+    uint64_t* row = s_row[threadIdx.x];
     int bad_at = INT32_MAX;
     const int end = parse_line(a, C, L, row, &bad_at);
     if (end >= 0) {
@@ -444,11 +441,70 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
       }
       A.add(d);
       ++nrows;
-      L = end + 1;
-    } else {
-      first_bad = min(first_bad, bad_at);
-      L = (-1 - end) + 1;
+      return end + 1;
     }
+    first_bad = min(first_bad, bad_at);
+    return (-1 - end) + 1;
+  };
+
+  // line starts in [s0, s1): a position after '\n' (or the stream start).
+  // Each thread counts those of its SLICE positions four characters at a time
+  // (a '\n' byte is a zero byte of v ^ 0x0a0a0a0a), a workgroup scan places
+  // them, and thread t then parses lines t, t + 256, ...: the lanes of a wave
+  // walk the same fields of different lines side by side.
+  const int c0 = s0r + (int)threadIdx.x * SLICE;
+  const int c1 = min(c0 + SLICE, s1r);
+  auto starts = [&](int base, bool write) -> int {
+    int cnt = 0;
+    if (c0 < c1) {
+      if (w0 + c0 == 0) {  // the stream's first byte
+        if (write) s_ls[base] = (unsigned short)c0;
+        ++cnt;
+      }
+      const int lo = max(c0 - 1, 0), hi = c1 - 1;  // newline positions m in [lo, hi)
+      for (int m4 = lo & ~3; m4 < hi; m4 += 4) {
+        const uint32_t v = *(const __attribute__((address_space(3))) uint32_t*)(
+            (const __attribute__((address_space(3))) unsigned char*)s_buf + pad(m4));
+        const uint32_t x = v ^ 0x0A0A0A0Au;
+        uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per '\n'
+        if (m4 < lo) z &= 0xFFFFFFFFu << (8 * (lo - m4));
+        if (m4 + 4 > hi) z &= 0xFFFFFFFFu >> (8 * (m4 + 4 - hi));
+        while (z) {
+          const int bpos = __builtin_ctz(z) >> 3;
+          z &= z - 1;
+          if (write) s_ls[base + cnt] = (unsigned short)(m4 + bpos + 1);
+          ++cnt;
+        }
+      }
+    }
+    return cnt;
+  };
+  const int mine = starts(0, false);
+  // workgroup exclusive scan of the counts
+  int incl = mine;
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+#pragma unroll
+  for (int d = 1; d < 64; d <<= 1) {
+    const int y = __shfl_up(incl, d, 64);
+    if (lane >= d) incl += y;
+  }
+  if (lane == 63) s_wsum[wv] = incl;
+  __syncthreads();
+  int before = incl - mine, total = 0;
+  for (int k = 0; k < kThreads / 64; ++k) {
+    if (k < wv) before += s_wsum[k];
+    total += s_wsum[k];
+  }
+  if (total <= MAXLS) {
+    starts(before, true);
+    __syncthreads();
+    for (int k = threadIdx.x; k < total; k += kThreads) (void)take_line((int)s_ls[k]);
+  } else {
+    // too many lines for the table: each thread walks its own slice
+    int L = c0;
+    if (w0 + L > 0)
+      while (L < c1 && C.at(L - 1) != '\n') ++L;
+    while (L < c1) L = take_line(L);
   }
   if (first_bad != INT32_MAX) {
     atomicMin(&a.status->parse_off, (unsigned long long)(a.base_off + w0 + first_bad));
