@@ -117,3 +117,39 @@ def test_split_and_fp64_agree_and_split_is_exact_on_fp32_grid():
     # C3-like FP32 data is shifted within its binade: the digits are exact, so
     # the two modes differ only by FP64 summation order
     assert corr_scaled_err(spl["cov"], f64["cov"]) <= 1e-13
+
+
+@pytest.mark.parametrize("n", [1, 63, 64, 65, 40_001])
+def test_split_two_extras_partial_group(n):
+    """Split mode, FP32 row-major kernel: 132 FP32 columns (two groups of 128,
+    the second partial) placed between an int64 identifier and an FP64 extra
+    column, a row stride wider than the FP32 block, windows with a ragged
+    tail.  Integer pairs exact; the rest within 1e-9 correlation-scaled."""
+    print(f"two extras n={n}", flush=True)
+    L = lib()
+    F = 132
+    x = np.zeros((n, F + 4), dtype=np.float32)  # 4 unused FP32 slots at the row end
+    x[:, :F] = gauss.rows_host(7, n, F)
+    ident = np.arange(10**12, 10**12 + n, dtype=np.int64)  # large shift, small range
+    extra = np.random.default_rng(8).standard_normal(n) * 1e3 + 5e4
+    cols = [(L.STATS_I64, 1, 0, L.STATS_COL_IDENTIFIER)] + \
+           [(L.STATS_F32, 0, 4 * j, 0) for j in range(F)] + [(L.STATS_F64, 2, 0, 0)]
+    p = F + 2
+    cfg = L.make_config(cols, [4 * (F + 4), 8, 8], stream=current_stream(),
+                        precision=L.STATS_PREC_SPLIT_BF16, block_rows=8192)
+    raw, fin = _run(L, cfg, [to_dev(x), to_dev(ident), to_dev(extra)], n, p)
+    is_int = [True] + [False] * (F + 1)
+    st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(F)] + [extra], is_int)
+    assert raw["n"] == n
+    assert raw["s_int"][0] == st.s_int[0] and raw["C_int"][0][0] == st.C_int[0]
+    for j in range(p):
+        for k in (0, 1, F, F + 1):
+            a, b = min(j, k), max(j, k)
+            ref = float(st.C_exact[oracle.tri_index(p, a, b)])
+            sc = (abs(float(st.C_exact[oracle.tri_index(p, a, a)])) *
+                  abs(float(st.C_exact[oracle.tri_index(p, b, b)]))) ** 0.5
+            if not (is_int[a] and is_int[b]):
+                assert abs(raw["C_f64"][j, k] - ref) <= 1e-9 * max(sc, 1e-300), (j, k)
+    if n > 1:
+        ref = oracle.finalize(st, mask=range(1, p))
+        assert corr_scaled_err(fin["cov"], ref["cov"]) <= 1e-9
