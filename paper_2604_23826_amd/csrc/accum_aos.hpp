@@ -8,11 +8,11 @@ namespace acc {
 // Row-major FP64 rows through LDS by direct DMA: 16-byte global loads that
 // write LDS without passing through registers.  A stage is 256 consecutive
 // rows (256 * RS contiguous bytes); each wave fetches a quarter of it as
-// 1 KiB pieces.  NS stages rotate in LDS with NS - 1 of them in flight while
-// one is reduced, one row per lane per stage, so the HBM queue stays full
-// without staging registers.  Wave-level completion is tracked by the
-// vector-memory counter (loads retire in order); a workgroup barrier then
-// publishes the stage to the other waves and frees the slot reduced last.
+// 1 KiB pieces -- the 64 rows its own lanes reduce.  NS stages rotate in LDS
+// with NS - 1 of them in flight while one is reduced, one row per lane per
+// stage, so the HBM queue stays full without staging registers.  Completion
+// is tracked per wave by the vector-memory counter (loads retire in order);
+// no workgroup barrier is needed.
 template <int P>
 struct AosDma {
   static constexpr int RS = (8 * P + 15) / 16 * 16;  // row stride (checked on the host)
@@ -134,10 +134,10 @@ __global__ __launch_bounds__(kThreads, (P <= 12 ? 2 : 1)) void k_aos_dma(Args a)
     // stage t is this wave's oldest outstanding group of loads
     if (t + NS - 2 < nst) __builtin_amdgcn_s_waitcnt(VmWait<(NS - 2) * LPW>::imm);
     else __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
-    // stage t visible to every wave; the slot of stage t-1 is free.  (The
-    // completion wait above is the only one needed: a fenced barrier would
-    // also wait for the stages still in flight.)
-    __builtin_amdgcn_s_barrier();
+    // Wave w fetches rows [64w, 64w + 64) of every stage -- exactly the rows
+    // its lanes reduce -- so its own completion wait is the only
+    // synchronisation: the slot of stage t-1, refilled next, was read by
+    // this wave in the previous iteration.
     if (t + NS - 1 < nst) issue(t + NS - 1);
     v4u raw[8];
     lds_row<LPW>(lds0 + (uint32_t)(t % NS) * SB + threadIdx.x * RS, raw);
