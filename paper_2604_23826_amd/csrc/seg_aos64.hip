@@ -33,6 +33,9 @@ constexpr int kSB = kSR * kRS;  // stage bytes
 constexpr int kNS = 3;        // stages in LDS
 constexpr int kLPW = kSB / 1024 / 4;  // 1 KiB DMA pieces per wave per stage (4)
 
+// Cache-policy operand of the DMA loads: non-temporal (each row is read once).
+constexpr int kNonTemporal = 2;
+
 // s_waitcnt immediate: at most N vector-memory loads of this wave outstanding.
 template <int N>
 struct VmWait {
@@ -127,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
 #pragma unroll
       for (int j = 0; j < kLPW; ++j)
         __builtin_amdgcn_global_load_lds((const void*)(src + j * 1024),
-                                         (__attribute__((address_space(3))) void*)(dst + j * 1024), 16, 0, 0);
+                                         (__attribute__((address_space(3))) void*)(dst + j * 1024), 16, 0, kNonTemporal);
     };
 #pragma unroll
     for (int t = 0; t < kNS - 1; ++t)
