@@ -271,7 +271,7 @@ extern "C" void stats_close(stats_ctx* h) {
   collect_timings(h);
   void* bufs[] = {h->state[0], h->state[1], h->intf_dev, h->status_dev, h->rec,
                   h->fin_out, h->fin_scratch, h->sel_dev, h->raw_out, h->stage_dev[0],
-                  h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev};
+                  h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev, h->seg_part};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int k = 0; k < 2; ++k) {

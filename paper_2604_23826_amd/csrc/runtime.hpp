@@ -65,6 +65,8 @@ struct stats_ctx {
   int64_t seg_tile_rows = 0;
   int seg_wg_per_cu = 0;
   int64_t seg_cap_rt = 0;
+  uint64_t* seg_part = nullptr;  // partial states of the segmented merge's first stage
+  size_t seg_part_cap = 0;
 
   // text ingest: bytes consumed so far (offsets in parse errors)
   int64_t text_offset = 0;

@@ -4,11 +4,11 @@
 // The rows of group g are [row_offsets[g], row_offsets[g+1]).  Each group is
 // cut into row tiles of a tuned height; the persistent wide kernel takes
 // (row tile, super-tile) items from an atomic queue and writes one block
-// record per row tile; a segmented merge then folds each group's records, in
-// tile order, into that group's state (exact 128-bit totals for integer
-// columns, Chan co-moments otherwise), so results do not depend on the order
-// in which workgroups ran.  The three kernels (queue reset, persistent
-// reduction, segmented merge) are captured once in a hipGraph and replayed
+// record per row tile; a two-stage segmented merge then folds each group's
+// records, in tile order, into that group's state (exact 128-bit totals for
+// integer columns, Chan co-moments otherwise), so results do not depend on the
+// order in which workgroups ran.  The four kernels (queue reset, persistent
+// reduction, two merge stages) are captured once in a hipGraph and replayed
 // for every call; all call-dependent inputs (plane addresses, tile table,
 // tile count) live in device buffers the graph reads, so the graph stays valid
 // from one wave of groups to the next.
@@ -30,6 +30,8 @@ namespace st {
 namespace {
 
 constexpr int kMergeThreads = 256;
+constexpr int kMergeBatch = 8;  // records (or partial states) whose loads are in flight together
+constexpr int kChunk = 32;      // records per first-stage chunk
 
 struct ChanE {
   double n, mi, mj, m2;
@@ -51,78 +53,178 @@ __device__ inline void chan_merge(ChanE& a, const ChanE& b) {
   a.n = n;
 }
 
-// One workgroup per group: the group's state is updated in place.  The old
-// count and means are copied to LDS first (pair entries need the old means of
-// their columns, which the column entries overwrite).
-__global__ __launch_bounds__(kMergeThreads) void k_seg_merge(const uint64_t* __restrict__ rec,
-                                                             const int64_t* __restrict__ gt, int p,
-                                                             const uint8_t* __restrict__ intf,
-                                                             uint64_t* __restrict__ states,
-                                                             DevStatus* status) {
+// The records of one group are folded in two stages, each in a fixed order:
+//  1. k_seg_part: a chunk of at most kChunk consecutive records of one group
+//     is folded, in record order, into a partial state (same layout as a
+//     group state), so that a large group is spread over many workgroups;
+//  2. k_seg_fold: each group's state absorbs its chunks' partial states in
+//     chunk order.
+// Chunk boundaries depend only on the tile table, so the result does not
+// depend on the order in which workgroups ran.
+struct SegChunk {
+  int64_t k0, k1;  // records [k0, k1), all of one group
+};
+
+// Stage 1: grid-stride over the chunks (their count is read from device
+// memory, so a captured graph serves every call).
+__global__ __launch_bounds__(kMergeThreads) void k_seg_part(const uint64_t* __restrict__ rec,
+                                                            const SegChunk* __restrict__ chunks,
+                                                            const int64_t* __restrict__ nchunks, int p,
+                                                            const uint8_t* __restrict__ intf,
+                                                            uint64_t* __restrict__ parts,
+                                                            DevStatus* status) {
+  const Layout L = Layout::make(p);
+  const int64_t W = rec_words(p);
+  const int64_t E = p + L.T;
+  const int64_t nch = *nchunks;
+  uint32_t inexact = 0;
+  for (int64_t c = blockIdx.x; c < nch; c += gridDim.x) {
+    const int64_t k0 = chunks[c].k0, k1 = chunks[c].k1;
+    uint64_t* out = parts + c * L.words;
+    for (int64_t e = threadIdx.x; e < E; e += kMergeThreads) {
+      int i, j;
+      const bool is_col = e < p;
+      if (is_col) i = j = (int)e;
+      else tri_inv(p, e - p, &i, &j);
+      const int64_t t = is_col ? tri(p, i, i) : e - p;
+      const bool ii = intf[i], ij = intf[j];
+      ChanE acc{0.0, 0.0, 0.0, 0.0};
+      i128 exact = 0;
+      int64_t ntot = 0;
+      // every word of a batch is loaded before the first of its merges,
+      // which then run in record order
+      for (int64_t kb = k0; kb < k1; kb += kMergeBatch) {
+        uint64_t nbw[kMergeBatch], Kiw[kMergeBatch], Kjw[kMergeBatch], Siw[kMergeBatch],
+            Sjw[kMergeBatch], Qw[kMergeBatch];
+#pragma unroll
+        for (int u = 0; u < kMergeBatch; ++u) {
+          nbw[u] = Kiw[u] = Kjw[u] = Siw[u] = Sjw[u] = Qw[u] = 0;
+          if (kb + u < k1) {
+            const uint64_t* r = rec + (kb + u) * W;
+            nbw[u] = r[0];
+            Kiw[u] = r[2 + i];
+            Kjw[u] = r[2 + j];
+            Siw[u] = r[2 + p + i];
+            Sjw[u] = r[2 + p + j];
+            Qw[u] = r[2 + 2 * p + t];
+          }
+        }
+#pragma unroll
+        for (int u = 0; u < kMergeBatch; ++u) {
+          const int64_t nb = (int64_t)nbw[u];
+          if (nb == 0) continue;
+          const double nbd = (double)nb;
+          const double Si = __longlong_as_double((long long)Siw[u]);
+          const double Sj = __longlong_as_double((long long)Sjw[u]);
+          const double Qij = __longlong_as_double((long long)Qw[u]);
+          ChanE b;
+          b.n = nbd;
+          b.mi = (ii ? (double)(int64_t)Kiw[u] : __longlong_as_double((long long)Kiw[u])) + Si / nbd;
+          b.mj = (ij ? (double)(int64_t)Kjw[u] : __longlong_as_double((long long)Kjw[u])) + Sj / nbd;
+          b.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
+          chan_merge(acc, b);
+          ntot += nb;
+          if (is_col && ii) {
+            const int64_t K = (int64_t)Kiw[u];
+            if (!(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
+            exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
+          } else if (!is_col && ii && ij) {
+            const i128 Ki = (i128)(int64_t)Kiw[u], Kj = (i128)(int64_t)Kjw[u];
+            exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj +
+                     (i128)nb * Ki * Kj;
+          }
+        }
+      }
+      if (is_col) {
+        store_i128(out + L.off_s + 2 * i, exact);
+        out[L.off_mu + i] = (uint64_t)__double_as_longlong(acc.mi);
+        if (e == 0) {
+          out[0] = (uint64_t)ntot;
+          out[1] = 0;
+        }
+      } else {
+        store_i128(out + L.off_C + 2 * t, exact);
+        out[L.off_M2 + t] = (uint64_t)__double_as_longlong(acc.m2);
+      }
+    }
+  }
+  if (inexact) atomicOr(&status->bits, ST_INEXACT);
+}
+
+// Stage 2: one workgroup per group; the group's state is updated in place.
+// The old count and means are copied to LDS first (pair entries need the old
+// means of their columns, which the column entries overwrite).
+__global__ __launch_bounds__(kMergeThreads) void k_seg_fold(const uint64_t* __restrict__ parts,
+                                                            const int64_t* __restrict__ gc, int p,
+                                                            const uint8_t* __restrict__ intf,
+                                                            uint64_t* __restrict__ states) {
   extern __shared__ double s_mu[];  // p old means, then old n
   const int g = blockIdx.x;
-  const int64_t t0 = gt[g], t1 = gt[g + 1];
-  if (t0 == t1) return;
+  const int64_t c0 = gc[g], c1 = gc[g + 1];
+  if (c0 == c1) return;
   const Layout L = Layout::make(p);
   uint64_t* st = states + (int64_t)g * L.words;
   for (int i = threadIdx.x; i < p; i += kMergeThreads)
     s_mu[i] = __longlong_as_double((long long)st[L.off_mu + i]);
   if (threadIdx.x == 0) s_mu[p] = (double)(int64_t)st[0];
   __syncthreads();
-  const double n_old = s_mu[p];
-  const int64_t W = rec_words(p);
+  const int64_t n_old = (int64_t)s_mu[p];
   const int64_t E = p + L.T;
-  uint32_t inexact = 0;
   for (int64_t e = threadIdx.x; e < E; e += kMergeThreads) {
     int i, j;
     const bool is_col = e < p;
     if (is_col) i = j = (int)e;
     else tri_inv(p, e - p, &i, &j);
-    const int64_t t = is_col ? tri(p, i, i) : e - p;
-    const bool ii = intf[i], ij = intf[j];
+    const int64_t t = is_col ? -1 : e - p;
+    const bool both = intf[i] && intf[j];
     ChanE acc;
-    acc.n = n_old;
+    acc.n = (double)n_old;
     acc.mi = s_mu[i];
     acc.mj = s_mu[j];
     acc.m2 = is_col ? 0.0 : __longlong_as_double((long long)st[L.off_M2 + t]);
-    i128 exact = is_col ? load_i128(st + L.off_s + 2 * i) : load_i128(st + L.off_C + 2 * t);
-    int64_t ntot = (int64_t)st[0];
-    for (int64_t k = t0; k < t1; ++k) {
-      const uint64_t* r = rec + k * W;
-      const int64_t nb = (int64_t)r[0];
-      if (nb == 0) continue;
-      const double nbd = (double)nb;
-      const uint64_t Kiw = r[2 + i], Kjw = r[2 + j];
-      const double Si = __longlong_as_double((long long)r[2 + p + i]);
-      const double Sj = __longlong_as_double((long long)r[2 + p + j]);
-      const double Qij = __longlong_as_double((long long)r[2 + 2 * p + t]);
-      ChanE b;
-      b.n = nbd;
-      b.mi = (ii ? (double)(int64_t)Kiw : __longlong_as_double((long long)Kiw)) + Si / nbd;
-      b.mj = (ij ? (double)(int64_t)Kjw : __longlong_as_double((long long)Kjw)) + Sj / nbd;
-      b.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
-      chan_merge(acc, b);
-      ntot += nb;
-      if (is_col && ii) {
-        const int64_t K = (int64_t)Kiw;
-        if (!(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
-        exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
-      } else if (!is_col && ii && ij) {
-        const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
-        exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj +
-                 (i128)nb * Ki * Kj;
+    const int64_t xo = is_col ? L.off_s + 2 * i : L.off_C + 2 * t;
+    i128 exact = load_i128(st + xo);
+    int64_t ntot = n_old;
+    for (int64_t cb = c0; cb < c1; cb += kMergeBatch) {
+      uint64_t nw[kMergeBatch], mi[kMergeBatch], mj[kMergeBatch], m2[kMergeBatch], xl[kMergeBatch],
+          xh[kMergeBatch];
+#pragma unroll
+      for (int u = 0; u < kMergeBatch; ++u) {
+        nw[u] = mi[u] = mj[u] = m2[u] = xl[u] = xh[u] = 0;
+        if (cb + u < c1) {
+          const uint64_t* s = parts + (cb + u) * L.words;
+          nw[u] = s[0];
+          mi[u] = s[L.off_mu + i];
+          mj[u] = s[L.off_mu + j];
+          if (!is_col) m2[u] = s[L.off_M2 + t];
+          xl[u] = s[xo];
+          xh[u] = s[xo + 1];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < kMergeBatch; ++u) {
+        if (nw[u] == 0) continue;
+        ChanE b;
+        b.n = (double)(int64_t)nw[u];
+        b.mi = __longlong_as_double((long long)mi[u]);
+        b.mj = __longlong_as_double((long long)mj[u]);
+        b.m2 = __longlong_as_double((long long)m2[u]);
+        chan_merge(acc, b);
+        ntot += (int64_t)nw[u];
+        if (is_col || both) {
+          const uint64_t w[2] = {xl[u], xh[u]};
+          exact += load_i128(w);
+        }
       }
     }
+    store_i128(st + xo, exact);
     if (is_col) {
-      store_i128(st + L.off_s + 2 * i, exact);
       st[L.off_mu + i] = (uint64_t)__double_as_longlong(acc.mi);
       if (e == 0) st[0] = (uint64_t)ntot;
     } else {
-      store_i128(st + L.off_C + 2 * t, exact);
       st[L.off_M2 + t] = (uint64_t)__double_as_longlong(acc.m2);
     }
   }
-  if (inexact) atomicOr(&status->bits, ST_INEXACT);
 }
 
 // Per-group mean and covariance of the selected columns.
@@ -218,7 +320,8 @@ void tune_cache_store(const std::string& key, const Tuned& t) {
 }  // namespace
 
 // Device buffers of a groups handle (inside aux2): slot table, super-tile
-// list, row tiles, per-group tile offsets, tile count, queue head.
+// list, row tiles, per-group tile offsets, tile count, queue head, merge
+// chunks, per-group chunk offsets, chunk count.
 struct SegBuffers {
   wide::SlotInfo* slots;
   int2* sts;
@@ -226,7 +329,13 @@ struct SegBuffers {
   int64_t* gt;
   int64_t* nrt;
   unsigned long long* counter;
+  SegChunk* chunks;
+  int64_t* gc;
+  int64_t* nch;
 };
+
+// Upper bound on the merge chunks of cap_rt records in ngroups groups.
+static int64_t chunk_cap(int64_t cap_rt, int ngroups) { return cap_rt / kChunk + ngroups; }
 
 static SegBuffers seg_layout(stats_ctx* h, int ntiles_st, int64_t cap_rt, size_t* total) {
   auto al = [](size_t x) { return (x + 255) / 256 * 256; };
@@ -244,6 +353,12 @@ static SegBuffers seg_layout(stats_ctx* h, int ntiles_st, int64_t cap_rt, size_t
   b.nrt = (int64_t*)(base + off);
   off += 256;
   b.counter = (unsigned long long*)(base + off);
+  off += 256;
+  b.chunks = (SegChunk*)(base + off);
+  off += al(sizeof(SegChunk) * chunk_cap(cap_rt, h->ngroups));
+  b.gc = (int64_t*)(base + off);
+  off += al(sizeof(int64_t) * (h->ngroups + 1));
+  b.nch = (int64_t*)(base + off);
   off += 256;
   *total = off;
   return b;
@@ -461,11 +576,21 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
   build_rowtiles(row_offsets, h->ngroups, tu.tile_rows, INT64_MAX, &tiles, &gt);
   const int64_t nt = (int64_t)tiles.size();
   if (nt == 0) return STATS_OK;
+  // merge chunks: runs of at most kChunk consecutive records of one group
+  std::vector<SegChunk> chunks;
+  std::vector<int64_t> gc(h->ngroups + 1, 0);
+  for (int g = 0; g < h->ngroups; ++g) {
+    gc[g] = (int64_t)chunks.size();
+    for (int64_t k = gt[g]; k < gt[g + 1]; k += kChunk) chunks.push_back(SegChunk{k, std::min(k + kChunk, gt[g + 1])});
+  }
+  gc[h->ngroups] = (int64_t)chunks.size();
+  const int64_t nch = (int64_t)chunks.size();
   // capacity grows in steps so that the graph is rarely rebuilt
   int64_t cap_rt = std::max<int64_t>(h->seg_cap_rt, 1024);
   while (cap_rt < nt) cap_rt *= 2;
   const size_t rec_need = (size_t)(cap_rt * rec_words(p) * 8);
-  if (cap_rt != h->seg_cap_rt || rec_need > h->rec_cap) {
+  const size_t part_need = (size_t)chunk_cap(cap_rt, h->ngroups) * (size_t)Layout::make(p).words * 8;
+  if (cap_rt != h->seg_cap_rt || rec_need > h->rec_cap || part_need > h->seg_part_cap) {
     if (h->graph_exec) {
       (void)hipGraphExecDestroy(h->graph_exec);
       h->graph_exec = nullptr;
@@ -482,12 +607,21 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
     rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, rec_need);
     if (rc) return rc;
   }
+  if (part_need > h->seg_part_cap) {
+    rc = ensure_dev(h, (void**)&h->seg_part, &h->seg_part_cap, part_need);
+    if (rc) return rc;
+  }
   h->seg_cap_rt = cap_rt;
   hipError_t e = hipMemcpyAsync(B.rowtiles, tiles.data(), sizeof(wide::SegTile) * nt,
                                 hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(B.gt, gt.data(), sizeof(int64_t) * gt.size(), hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipMemcpyAsync(B.nrt, &nt, 8, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B.chunks, chunks.data(), sizeof(SegChunk) * nch, hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(B.gc, gc.data(), sizeof(int64_t) * gc.size(), hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(B.nch, &nch, 8, hipMemcpyHostToDevice, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);  // host vectors go out of scope
   if (e != hipSuccess) return hip_fail(h, e, "uploading segment tables");
 
@@ -514,9 +648,11 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
     e = hipStreamBeginCapture(h->cap_stream, hipStreamCaptureModeThreadLocal);
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamBeginCapture");
     seg_launch(h, aos64, a, sa, ST, nwg, h->cap_stream);
+    hipLaunchKernelGGL(k_seg_part, dim3((unsigned)(num_cus(h->device) * 8)), dim3(kMergeThreads), 0,
+                       h->cap_stream, h->rec, B.chunks, B.nch, p, h->intf_dev, h->seg_part, h->status_dev);
     const size_t shm = sizeof(double) * (size_t)(p + 1);
-    hipLaunchKernelGGL(k_seg_merge, dim3((unsigned)h->ngroups), dim3(kMergeThreads), shm,
-                       h->cap_stream, h->rec, B.gt, p, h->intf_dev, h->state[0], h->status_dev);
+    hipLaunchKernelGGL(k_seg_fold, dim3((unsigned)h->ngroups), dim3(kMergeThreads), shm,
+                       h->cap_stream, h->seg_part, B.gc, p, h->intf_dev, h->state[0]);
     e = hipStreamEndCapture(h->cap_stream, &h->graph);
     if (e != hipSuccess) return hip_fail(h, e, "hipStreamEndCapture");
     e = hipGraphInstantiate(&h->graph_exec, h->graph, nullptr, nullptr, 0);
