@@ -34,7 +34,7 @@ constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = 256;       // bytes of line starts per thread
 constexpr int MAXLS = 4096;      // line starts per workgroup kept in the table
 constexpr int STAGE = 16 + SEG + MAXLINE;
-constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 1) * 16;
+constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 2) * 16;  // room for word reads past the end
 
 struct Args {
   const char* buf;
@@ -70,7 +70,43 @@ struct Cur {
     if (pos >= S->lim) return -1;
     return ((const __attribute__((address_space(3))) unsigned char*)S->s)[pad(pos)];
   }
+  // The four bytes at pos .. pos + 3 (the first in the low byte), from two
+  // aligned LDS words; bytes at or past lim read as 0xFF.  pos >= 0.
+  __device__ inline uint32_t word4(int pos) const {
+    const int a = pos & ~3;
+    const __attribute__((address_space(3))) unsigned char* b =
+        (const __attribute__((address_space(3))) unsigned char*)S->s;
+    const uint32_t lo = *(const __attribute__((address_space(3))) uint32_t*)(b + pad(a));
+    const uint32_t hi = *(const __attribute__((address_space(3))) uint32_t*)(b + pad(a + 4));
+    uint32_t v = __builtin_amdgcn_alignbyte(hi, lo, (uint32_t)(pos & 3));
+    const int room = S->lim - pos;
+    if (room < 4) v |= room <= 0 ? 0xFFFFFFFFu : (0xFFFFFFFFu << (8 * room));
+    return v;
+  }
 };
+
+// Leading decimal digits of a 4-byte word (first character in the low byte):
+// their count k (0..4) and value.  A byte is a digit when its high nibble is
+// 3 and its low nibble is below 10 (low nibble + 6 does not carry into bit 4).
+__device__ inline int digit_run(uint32_t v, uint32_t* val) {
+  const uint32_t m = ((v & 0xF0F0F0F0u) ^ 0x30303030u) | (((v & 0x0F0F0F0Fu) + 0x06060606u) & 0xF0F0F0F0u);
+  const int k = m ? (__builtin_ctz(m) >> 3) : 4;
+  // digit values moved to the top k bytes (leading zero bytes add nothing);
+  // then bytes (b0 b1 b2 b3) -> (10 b0 + b1, 10 b2 + b3) -> 100 (..) + (..)
+  const uint32_t y = k ? (v & 0x0F0F0F0Fu) << (8 * (4 - k)) : 0u;
+  const uint32_t t = y * 10u + (y >> 8);
+  *val = (t & 0xFFu) * 100u + ((t >> 16) & 0xFFu);
+  return k;
+}
+
+// Decimal digits of v < 10^4 without leading zeros.
+__device__ inline int sig_count(uint32_t v) {
+  return (v >= 1000u) + (v >= 100u) + (v >= 10u) + (v >= 1u);
+}
+
+__device__ inline uint32_t pow10_small(int k) {  // 10^k, 1 <= k <= 4
+  return k >= 3 ? (k == 4 ? 10000u : 1000u) : (k == 2 ? 100u : 10u);
+}
 
 __device__ inline int bitlen64(uint64_t v) { return v ? 64 - __builtin_clzll(v) : 0; }
 __device__ inline int bitlen128(u128 v) {
@@ -113,11 +149,21 @@ __device__ inline double round_to_double(u128 w, bool sticky, int e2, bool neg) 
   return neg ? -r : r;
 }
 
-__device__ inline uint64_t pow5_u64(int k) {  // 5^k for k <= 27
+struct Pow5 {
+  uint64_t v[28];  // 5^k, k <= 27 (5^27 < 2^63)
+};
+constexpr Pow5 make_pow5() {
+  Pow5 t{};
   uint64_t r = 1;
-  for (int i = 0; i < k; ++i) r *= 5;
-  return r;
+  for (int k = 0; k < 28; ++k) {
+    t.v[k] = r;
+    r *= 5;
+  }
+  return t;
 }
+__constant__ Pow5 kPow5 = make_pow5();
+
+__device__ inline uint64_t pow5_u64(int k) { return kPow5.v[k]; }
 
 // Exact w * 10^q for w < 2^64 and |q| <= 27: w 5^q fits 128 bits for q > 0;
 // for q < 0 the quotient w 2^k / 5^-q (k chosen for 54..56 bits) comes from
@@ -184,32 +230,47 @@ __device__ inline double decimal_value(u128 w, int nd, int q, bool sticky, bool 
   return slow_decimal(w, q, sticky, neg);
 }
 
+// Digits from position i on, four per step, into w (significant digits
+// counted in nd; q lowered by one per digit when frac).  Returns the character
+// after the digits (-1 past the text), or kTooLong when the run would give w
+// more than 19 significant digits (w, nd, i are then unspecified).
+constexpr int kTooLong = -2;
+__device__ inline int digit_steps(const Cur& C, int& i, uint64_t& w, int& nd, int& q, bool frac) {
+  for (;;) {
+    const uint32_t v = C.word4(i);
+    uint32_t val;
+    const int k = digit_run(v, &val);
+    if (k) {
+      const int sig = w ? k : sig_count(val);
+      if (nd + sig > 19) return kTooLong;
+      w = w * pow10_small(k) + val;
+      nd += sig;
+      i += k;
+      if (frac) q -= k;
+    }
+    if (k < 4) return i >= C.S->lim ? -1 : (int)((v >> (8 * k)) & 0xFFu);
+  }
+}
+
 __device__ inline int parse_field(Cur& C, int f, bool is_int, uint64_t* bits) {
   int i = f;
   int c = C.at(i);
   bool neg = false;
   if (c == '-' || c == '+') {
     neg = c == '-';
-    c = C.at(++i);
+    ++i;
   }
   uint64_t w = 0;
   int nd = 0;
   int q = 0;
-  bool digits = false;
-  while (c >= '0' && c <= '9') {
-    digits = true;
-    const int d = c - '0';
-    if (w != 0 || d != 0) {
-      if (nd == 19) {
-        const Parsed r = parse_wide(*C.S, f, is_int);
-        *bits = r.bits;
-        return r.pos;
-      }
-      w = w * 10 + (uint64_t)d;
-      ++nd;
-    }
-    c = C.at(++i);
+  const int i0 = i;
+  c = digit_steps(C, i, w, nd, q, false);
+  if (c == kTooLong) {
+    const Parsed r = parse_wide(*C.S, f, is_int);
+    *bits = r.bits;
+    return r.pos;
   }
+  bool digits = i > i0;
   if (is_int) {
     if (!digits || nd > 18) return -1 - i;
     if (c != ',' && c != '\n' && c != -1) return -1 - i;
@@ -218,24 +279,15 @@ __device__ inline int parse_field(Cur& C, int f, bool is_int, uint64_t* bits) {
     return i;
   }
   if (c == '.') {
-    c = C.at(++i);
-    while (c >= '0' && c <= '9') {
-      digits = true;
-      const int d = c - '0';
-      if (w == 0 && d == 0) {
-        --q;
-      } else {
-        if (nd == 19) {
-          const Parsed r = parse_wide(*C.S, f, is_int);
-          *bits = r.bits;
-          return r.pos;
-        }
-        w = w * 10 + (uint64_t)d;
-        ++nd;
-        --q;
-      }
-      c = C.at(++i);
+    ++i;
+    const int i1 = i;
+    c = digit_steps(C, i, w, nd, q, true);
+    if (c == kTooLong) {
+      const Parsed r = parse_wide(*C.S, f, is_int);
+      *bits = r.bits;
+      return r.pos;
     }
+    digits |= i > i1;
   }
   if (!digits) return -1 - i;
   if (c == 'e' || c == 'E') {
@@ -367,7 +419,7 @@ __device__ inline int parse_line(const Args& a, Cur& C, int L, uint64_t* row, in
 
 template <int P>
 __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
-  __shared__ unsigned char s_buf[STAGE_PADDED];
+  __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
   __shared__ uint64_t s_row[kThreads][P];
   __shared__ uint64_t sKb[P];
   __shared__ unsigned long long s_n;
