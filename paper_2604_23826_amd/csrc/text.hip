@@ -28,10 +28,12 @@
 namespace st {
 namespace text {
 
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
 constexpr int kThreads = 256;
 constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
 constexpr int MAXLINE = 4096;    // longest line accepted
-constexpr int SLICE = 256;       // bytes of line starts per thread
+constexpr int SLICE = SEG / 256;  // bytes of line starts per thread (one slice per thread)
 constexpr int MAXLS = 4096;      // line starts per workgroup kept in the table
 constexpr int STAGE = 16 + SEG + MAXLINE;
 constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 2) * 16;  // room for word reads past the end
@@ -454,24 +456,11 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   const Stage S{s_buf, w0, n, (int)(min(a.nend, w0 + (int64_t)n) - w0)};
   const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);  // relative positions
 
-  // block shift: the first line starting in [s0, s1) (zeros if none parses)
-  if (threadIdx.x == 0) {
-    Cur C0(S);
-    int L = s0r;
-    if (s0 > 0) {
-      while (L < s1r && C0.at(L - 1) != '\n') ++L;
-    }
-    for (int c = 0; c < P; ++c) s_row[0][c] = 0;
-    int bad_at;
-    if (L >= s1r || parse_line(a, C0, L, s_row[0], &bad_at) < 0)
-      for (int c = 0; c < P; ++c) s_row[0][c] = 0;
-    for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
-  }
-  __syncthreads();
-  // shift words: int64 for integer columns, FP64 bits otherwise
+  // shift words (int64 for integer columns, FP64 bits otherwise): the row of
+  // the workgroup's first line, zeros if it does not parse; set below
   uint64_t K64[P];
 #pragma unroll
-  for (int c = 0; c < P; ++c) K64[c] = sKb[c];
+  for (int c = 0; c < P; ++c) K64[c] = 0;
 
   acc::Acc<P> A;
   A.zero();
@@ -479,20 +468,23 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   unsigned long long nrows = 0;
   int first_bad = INT32_MAX;
   Cur C(S);
+  auto add_row = [&](const uint64_t* row) {
+    double d[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const uint64_t b = row[c];
+      d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
+                                      : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
+    }
+    A.add(d);
+    ++nrows;
+  };
   auto take_line = [&](int L) -> int {  // parses and accumulates one line; returns the next position
     uint64_t* row = s_row[threadIdx.x];
     int bad_at = INT32_MAX;
     const int end = parse_line(a, C, L, row, &bad_at);
     if (end >= 0) {
-      double d[P];
-#pragma unroll
-      for (int c = 0; c < P; ++c) {
-        const uint64_t b = row[c];
-        d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
-                                        : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
-      }
-      A.add(d);
-      ++nrows;
+      add_row(row);
       return end + 1;
     }
     first_bad = min(first_bad, bad_at);
@@ -500,38 +492,50 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
   };
 
   // line starts in [s0, s1): a position after '\n' (or the stream start).
-  // Each thread counts those of its SLICE positions four characters at a time
-  // (a '\n' byte is a zero byte of v ^ 0x0a0a0a0a), a workgroup scan places
-  // them, and thread t then parses lines t, t + 256, ...: the lanes of a wave
-  // walk the same fields of different lines side by side.
+  // Thread t finds the newlines of its SLICE positions in one pass of 16-byte
+  // LDS reads, keeping them as a bit mask (a '\n' byte is a zero byte of
+  // v ^ 0x0a0a0a0a); a workgroup scan of the counts places them, and thread t
+  // then parses lines t, t + 256, ...: the lanes of a wave walk the same
+  // fields of different lines side by side.
+  static_assert(SLICE * kThreads == SEG && SLICE % 16 == 0, "one slice per thread");
+  constexpr int NV = SLICE / 16 + 1;         // 16-byte reads per slice (it may start mid-vector)
+  constexpr int NM = (16 * NV + 31) / 32;    // 32-bit mask words
   const int c0 = s0r + (int)threadIdx.x * SLICE;
   const int c1 = min(c0 + SLICE, s1r);
-  auto starts = [&](int base, bool write) -> int {
-    int cnt = 0;
-    if (c0 < c1) {
-      if (w0 + c0 == 0) {  // the stream's first byte
-        if (write) s_ls[base] = (unsigned short)c0;
-        ++cnt;
-      }
-      const int lo = max(c0 - 1, 0), hi = c1 - 1;  // newline positions m in [lo, hi)
-      for (int m4 = lo & ~3; m4 < hi; m4 += 4) {
-        const uint32_t v = *(const __attribute__((address_space(3))) uint32_t*)(
-            (const __attribute__((address_space(3))) unsigned char*)s_buf + pad(m4));
-        const uint32_t x = v ^ 0x0A0A0A0Au;
-        uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per '\n'
-        if (m4 < lo) z &= 0xFFFFFFFFu << (8 * (lo - m4));
-        if (m4 + 4 > hi) z &= 0xFFFFFFFFu >> (8 * (m4 + 4 - hi));
-        while (z) {
-          const int bpos = __builtin_ctz(z) >> 3;
-          z &= z - 1;
-          if (write) s_ls[base + cnt] = (unsigned short)(m4 + bpos + 1);
-          ++cnt;
+  // newline positions m in [mlo, mhi) start the lines c0 .. c1 - 1; bit b of the
+  // mask is position mb + b
+  const int mlo = max(c0 - 1, 0), mhi = c1 - 1;
+  const int mb = mlo & ~15;
+  uint32_t nl[NM];
+#pragma unroll
+  for (int j = 0; j < NM; ++j) nl[j] = 0;
+  int mine = 0;
+  if (c0 < c1) {
+    if (w0 + c0 == 0) ++mine;  // the stream's first byte
+#pragma unroll
+    for (int k = 0; k < NV; ++k) {
+      const int m16 = mb + 16 * k;
+      if (m16 < mhi) {
+        const u32x4 v = *(const __attribute__((address_space(3))) u32x4*)(
+            (const __attribute__((address_space(3))) unsigned char*)s_buf + pad(m16));
+        uint32_t bits = 0;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+          const uint32_t x = v[e] ^ 0x0A0A0A0Au;
+          const uint32_t z = ~(((x & 0x7F7F7F7Fu) + 0x7F7F7F7Fu) | x | 0x7F7F7F7Fu);  // 0x80 per '\n'
+          // bits 7, 15, 23, 31 -> bits 0..3 (the four shifted copies do not overlap)
+          bits |= (((z >> 7) * 0x204081u) >> 21 & 0xFu) << (4 * e);
         }
+        // keep positions in [mlo, mhi)
+        const int b0 = mlo - m16, b1 = mhi - m16;
+        if (b0 > 0) bits &= 0xFFFFu << b0;
+        if (b1 < 16) bits &= (1u << b1) - 1u;
+        nl[k >> 1] |= bits << (16 * (k & 1));
       }
     }
-    return cnt;
-  };
-  const int mine = starts(0, false);
+#pragma unroll
+    for (int j = 0; j < NM; ++j) mine += __builtin_popcount(nl[j]);
+  }
   // workgroup exclusive scan of the counts
   int incl = mine;
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
@@ -548,11 +552,49 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
     total += s_wsum[k];
   }
   if (total <= MAXLS) {
-    starts(before, true);
+    if (c0 < c1) {
+      int at = before;
+      if (w0 + c0 == 0) s_ls[at++] = (unsigned short)c0;
+#pragma unroll
+      for (int j = 0; j < NM; ++j) {
+        uint32_t m = nl[j];
+        while (m) {
+          s_ls[at++] = (unsigned short)(mb + 32 * j + __builtin_ctz(m) + 1);
+          m &= m - 1;
+        }
+      }
+    }
     __syncthreads();
-    for (int k = threadIdx.x; k < total; k += kThreads) (void)take_line((int)s_ls[k]);
+    // round 0 parses only; line 0 is the workgroup's first line, whose row
+    // (copied by thread 0 before the barrier) is the block shift
+    int end0 = -1, bad0 = INT32_MAX;
+    uint64_t* row0 = s_row[threadIdx.x];
+    if ((int)threadIdx.x < total) end0 = parse_line(a, C, (int)s_ls[threadIdx.x], row0, &bad0);
+    if (threadIdx.x == 0)
+      for (int c = 0; c < P; ++c) sKb[c] = end0 >= 0 ? row0[c] : 0;
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < P; ++c) K64[c] = sKb[c];
+    if ((int)threadIdx.x < total) {
+      if (end0 >= 0) add_row(row0);
+      else first_bad = min(first_bad, bad0);
+    }
+    for (int k = threadIdx.x + kThreads; k < total; k += kThreads) (void)take_line((int)s_ls[k]);
   } else {
-    // too many lines for the table: each thread walks its own slice
+    // too many lines for the table: the shift from the first line, found by
+    // one thread, then each thread walks its own slice
+    if (threadIdx.x == 0) {
+      int L = s0r;
+      if (s0 > 0)
+        while (L < s1r && C.at(L - 1) != '\n') ++L;
+      int bad_at;
+      if (L >= s1r || parse_line(a, C, L, s_row[0], &bad_at) < 0)
+        for (int c = 0; c < P; ++c) s_row[0][c] = 0;
+      for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
+    }
+    __syncthreads();
+#pragma unroll
+    for (int c = 0; c < P; ++c) K64[c] = sKb[c];
     int L = c0;
     if (w0 + L > 0)
       while (L < c1 && C.at(L - 1) != '\n') ++L;
@@ -606,7 +648,6 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   const int64_t nblocks = (nend + SEG - 1) / SEG;
   if (nblocks == 0) return STATS_OK;
   const int64_t W = rec_words(p);
-  const Layout L = Layout::make(p);
   int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
   if (rc) return rc;
   Args a;
