@@ -42,9 +42,19 @@ struct Args {
   int lds_mat;  // A and V in dynamic LDS after the rotation tables
 };
 
-// Round-robin schedule on m (even) players: player at position pos in round r.
+// Round-robin schedule on m (even) players: player at position pos in round
+// r (0 <= pos < m, 0 <= r < m - 1).
 __device__ inline int rr_player(int pos, int r, int m) {
-  return pos == 0 ? 0 : ((pos - 1 + r) % (m - 1)) + 1;
+  if (pos == 0) return 0;
+  const int x = pos - 1 + r;  // < 2 (m - 1)
+  return (x >= m - 1 ? x - (m - 1) : x) + 1;
+}
+
+// The two players of pair k in round r, smaller first.
+__device__ inline void rr_pair(int k, int r, int m, int& a, int& b) {
+  const int x = rr_player(k, r, m), y = rr_player(m - 1 - k, r, m);
+  a = min(x, y);
+  b = max(x, y);
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
@@ -66,15 +76,13 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   __shared__ int s_rot;
   const int m = q + (q & 1);  // players (a dummy when q is odd)
   const int npairs = m / 2;
-  extern __shared__ double s_dyn[];  // c[npairs], s[npairs], t[npairs], apq[npairs], pair p/q
+  extern __shared__ double s_dyn[];  // c[npairs], s[npairs], t[npairs], apq[npairs], A, V
   double* rc = s_dyn;
   double* rs = rc + npairs;
   double* rt = rs + npairs;
   double* rapq = rt + npairs;
-  int* pp = (int*)(rapq + npairs);
-  int* pq = pp + npairs;
   double* A = f.scratch;
-  if (f.lds_mat) A = s_dyn + 4 * npairs + (npairs + 1) / 2 * 2;  // after pp, pq (8-byte aligned)
+  if (f.lds_mat) A = s_dyn + 4 * npairs;
   double* V = A + (int64_t)q * q;
 
   // ---- means and covariance ----
@@ -84,8 +92,11 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     mean[a] = f.intf[i] ? exact_mean(st, L, i, n)
                         : __longlong_as_double((long long)st[L.off_mu + i]);
   }
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
-    const int a = (int)(idx / q), b = (int)(idx % q);
+  // q <= 1024: every index below fits 32 bits (64-bit division is a long
+  // software sequence on the GPU)
+  const int qq = q * q;
+  for (int idx = tid; idx < qq; idx += nth) {
+    const int a = idx / q, b = idx % q;
     if (a > b) continue;
     const int i = f.sel[a], j = f.sel[b];  // sel ascending, so i <= j
     double v;
@@ -96,8 +107,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   }
   __syncthreads();
   // ---- correlation ----
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
-    const int a = (int)(idx / q), b = (int)(idx % q);
+  for (int idx = tid; idx < qq; idx += nth) {
+    const int a = idx / q, b = idx % q;
     const double caa = cov[(int64_t)a * q + a], cbb = cov[(int64_t)b * q + b];
     double v;
     if (caa == 0.0 || cbb == 0.0) v = __builtin_nan("");
@@ -110,7 +121,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   // ---- PCA input ----
   const double* M = f.pca_on ? cov : corr;
   int bad = 0;
-  for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) {
+  for (int idx = tid; idx < qq; idx += nth) {
     const double v = M[idx];
     if (!isfinite(v)) bad = 1;
     A[idx] = v;
@@ -119,7 +130,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   if (bad) atomicOr(&s_flag, 1);
   __syncthreads();
   if (s_flag) {
-    for (int64_t idx = tid; idx < (int64_t)q * q; idx += nth) evec[idx] = __builtin_nan("");
+    for (int idx = tid; idx < qq; idx += nth) evec[idx] = __builtin_nan("");
     for (int a = tid; a < q; a += nth) {
       ev[a] = varp[a] = cump[a] = __builtin_nan("");
     }
@@ -134,14 +145,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     for (int r = 0; r < m - 1; ++r) {
       // rotations of this round (one thread per disjoint pair)
       for (int k = tid; k < npairs; k += nth) {
-        int a = rr_player(k, r, m), b = rr_player(m - 1 - k, r, m);
-        if (a > b) {
-          const int x = a;
-          a = b;
-          b = x;
-        }
-        pp[k] = a;
-        pq[k] = b;
+        int a, b;
+        rr_pair(k, r, m, a, b);
         double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
         if (b < q) {
           apq = A[(int64_t)a * q + b];
@@ -164,17 +169,18 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
       __syncthreads();
       // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns); the blocks
       // of a round are disjoint, so a batch is loaded before it is written
-      const int64_t nblk = (int64_t)npairs * npairs;
-      for (int64_t base = tid; base < nblk; base += (int64_t)nth * kNB) {
+      const int nblk = npairs * npairs;
+      for (int base = tid; base < nblk; base += nth * kNB) {
         double x[kNB][4];
 #pragma unroll
         for (int e = 0; e < kNB; ++e) {
-          const int64_t idx = base + (int64_t)e * nth;
+          const int idx = base + e * nth;
           x[e][0] = x[e][1] = x[e][2] = x[e][3] = 0.0;
           if (idx >= nblk) continue;
-          const int u = (int)(idx / npairs), v = (int)(idx % npairs);
-          if (rs[u] == 0.0 && rs[v] == 0.0) continue;
-          const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
+          const int u = idx / npairs, v = idx % npairs;
+          int a, b, c2, d2;
+          rr_pair(u, r, m, a, b);
+          rr_pair(v, r, m, c2, d2);
           const bool bq = b < q, dq = d2 < q;
           x[e][0] = A[(int64_t)a * q + c2];
           if (dq) x[e][1] = A[(int64_t)a * q + d2];
@@ -183,12 +189,14 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
         }
 #pragma unroll
         for (int e = 0; e < kNB; ++e) {
-          const int64_t idx = base + (int64_t)e * nth;
+          const int idx = base + e * nth;
           if (idx >= nblk) continue;
-          const int u = (int)(idx / npairs), v = (int)(idx % npairs);
+          const int u = idx / npairs, v = idx % npairs;
           const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
           if (su == 0.0 && sv == 0.0) continue;
-          const int a = pp[u], b = pq[u], c2 = pp[v], d2 = pq[v];
+          int a, b, c2, d2;
+          rr_pair(u, r, m, a, b);
+          rr_pair(v, r, m, c2, d2);
           const bool bq = b < q, dq = d2 < q;
           const double x00 = x[e][0], x01 = x[e][1], x10 = x[e][2], x11 = x[e][3];
           // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
@@ -211,13 +219,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
         }
       }
       // V <- V J
-      for (int64_t idx = tid; idx < (int64_t)q * npairs; idx += nth) {
-        const int row = (int)(idx / npairs), u = (int)(idx % npairs);
+      for (int idx = tid; idx < q * npairs; idx += nth) {
+        const int row = idx / npairs, u = idx % npairs;
+        int a, b;
+        rr_pair(u, r, m, a, b);
+        if (b >= q) continue;  // the dummy player of odd q
+        const double va = V[(int64_t)row * q + a], vb = V[(int64_t)row * q + b];
         const double s = rs[u];
         if (s == 0.0) continue;
-        const int a = pp[u], b = pq[u];
         const double c = rc[u];
-        const double va = V[(int64_t)row * q + a], vb = V[(int64_t)row * q + b];
         V[(int64_t)row * q + a] = c * va - s * vb;
         V[(int64_t)row * q + b] = s * va + c * vb;
       }
@@ -319,7 +329,7 @@ void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
   a.out = F.out;
   a.scratch = F.scratch;
   const int npairs = (F.q + (F.q & 1)) / 2;
-  size_t shm = (size_t)npairs * 4 * sizeof(double) + (size_t)(npairs + 1) / 2 * 2 * sizeof(double);
+  size_t shm = (size_t)npairs * 4 * sizeof(double);
   a.lds_mat = F.q <= kLdsQ;
   if (a.lds_mat) shm += 2 * sizeof(double) * (size_t)F.q * F.q;
   // one wave for the small matrices of the narrow path (its barriers cost
