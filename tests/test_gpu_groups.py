@@ -97,6 +97,40 @@ def test_waves_split_groups_and_graph_replays():
         L.stats_close(h1)
 
 
+def test_many_records_per_group_chunked_merge():
+    """1024-row tiles, so that groups have up to 98 records: the merge folds
+    runs of 32 records into partial states and then folds those into the
+    group state (exactly 32, 33 and 64 records, a ragged 98, an empty group),
+    in one call and in two waves cut inside the largest group."""
+    L = lib()
+    sizes = [32 * 1024, 32 * 1024 + 1, 100_000, 0, 64 * 1024, 7]
+    x, off = _rows(14, sizes)
+    d = to_dev(x)
+    G = len(sizes)
+    h = L.stats_open_groups(_cfg(L, block_rows=1024), G)
+    h2 = L.stats_open_groups(_cfg(L, block_rows=1024), G)
+    try:
+        L.stats_accumulate_segmented(h, [d], off)
+        cut = int(off[2]) + 40_960 + 5  # 40 whole tiles of group 2 in the first wave
+        for a, b in ((0, cut), (cut, int(off[-1]))):
+            L.stats_accumulate_segmented(h2, [d[a:]], np.clip(off, a, b) - a)
+        fin, fin2 = L.stats_finalize_groups(h, G, 32), L.stats_finalize_groups(h2, G, 32)
+        for g, n in enumerate(sizes):
+            r, r2 = L.stats_group_raw(h, g, 32), L.stats_group_raw(h2, g, 32)
+            assert r["n"] == r2["n"] == n
+            if n == 0:
+                continue
+            st = _check_group(r, x[off[g]:off[g + 1]])
+            _check_group(r2, x[off[g]:off[g + 1]])
+            ref = oracle.finalize(st, mask=range(1, 32))
+            assert corr_scaled_err(fin["cov"][g], ref["cov"]) <= 1e-12
+            assert corr_scaled_err(fin2["cov"][g], ref["cov"]) <= 1e-12
+            assert fin["cov"][g][0, 0] == fin2["cov"][g][0, 0] == ref["cov"][0, 0]
+    finally:
+        L.stats_close(h)
+        L.stats_close(h2)
+
+
 def test_groups_repeatable_and_reset():
     L = lib()
     sizes = [10_000, 2, 40_000]

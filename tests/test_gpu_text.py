@@ -109,6 +109,40 @@ def test_decimal_parse_bit_exact_vs_strtod(fmt):
     assert not bad, bad[:5]
 
 
+def test_short_lines_and_digit_runs():
+    """Segments with more line starts than the workgroup's line table (lines
+    of 4 to 7 bytes: each thread then walks its own slice), next to fields
+    whose digit runs (leading zeros, signs, 1 to 17 digits, with and without
+    point and exponent) start at every offset of the four-character steps.
+    Integers against strtoll exactly, decimals through strtod."""
+    L = lib()
+    rng = np.random.default_rng(6)
+    m = 60_000
+    short = b"".join(b"%d,%d\n" % (a, b) for a, b in zip(rng.integers(0, 10, m), rng.integers(1, 100, m)))
+    lines = []
+    for _ in range(8000):
+        nz = int(rng.integers(0, 6))
+        a = rng.choice([b"", b"-", b"+"]) + b"0" * nz + str(int(rng.integers(0, 10 ** int(rng.integers(1, 7))))).encode()
+        nd = int(rng.integers(1, 18))
+        digits = str(int(rng.integers(10 ** (nd - 1), 10 ** nd))).encode()
+        pt = int(rng.integers(0, nd + 1))
+        b = b"0" * int(rng.integers(0, 3)) + digits[:pt] + (b"." + digits[pt:] if pt < nd else b"")
+        if rng.random() < 0.2:
+            b += b"e%d" % int(rng.integers(-20, 21))
+        lines.append(a + b"," + b + b"\n")
+    txt = short + b"".join(lines) + short[: short.index(b"\n", len(short) // 2) + 1]
+    rows = oracle.parse_csv(txt, 2, [True, False])
+    h = L.stats_open(_cfg(L, p=2, int_cols=[True, False]))
+    try:
+        used = L.stats_accumulate_text(h, _text_dev(txt), len(txt), is_last=True)
+        assert used == len(txt)
+        raw = L.stats_raw(h, 2)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(rows), [True, False])
+    check_raw_against_oracle(raw, st, [True, False])
+
+
 def test_parse_errors_report_offsets():
     L = lib()
     good = b"1,2,3\n"
