@@ -82,6 +82,17 @@ def hbm_roofline(kernel, bytes_total, ms_total, launches, bytes_per_launch, traf
             "algorithmic_bytes_per_launch": round(bytes_per_launch)}
 
 
+def add_measured_read(roof, L, bufs, nbytes, stream, reps=3):
+    """Second denominator: the library's pure-read probe over the same
+    device buffers (best of reps), and the kernel's fraction of it."""
+    ms = min(L.stats_read_probe(bufs, nbytes, stream) for _ in range(reps))
+    gbs = sum(nbytes) / (ms / 1e3) / 1e9
+    roof["measured_read_gbs"] = round(gbs, 1)
+    roof["frac_of_measured_read"] = round(roof["achieved"] / gbs, 4)
+    roof["measured_read_bytes"] = int(sum(nbytes))
+    return roof
+
+
 def cov_err(a, b):
     import numpy as np
     d = np.sqrt(np.abs(np.diag(b)))
@@ -160,6 +171,8 @@ def run_share(args, L, torch, datagen):
     rows_per_launch = N * args.steps / max(launches, 1)
     roof = hbm_roofline("accum_small_p (p=10, int32x9 + fp64 planes)", N * args.steps * bpr, ms1 - ms0,
                         launches, rows_per_launch * bpr, traffic_from_profile(rows_per_launch))
+    if kind == L.STATS_MEM_DEVICE:
+        add_measured_read(roof, L, bases, [N * s for s in itemsz], stream)
     log(f"step {ms_per_step:.2f} ms, {rows_per_s:.3e} rows/s, kernel {roof['achieved']:.0f} GB/s")
     cpu = None
     if not args.no_cpu_baseline:
@@ -245,7 +258,7 @@ def run_c1(args, L, torch, datagen):
                     {"workload": f"table1_fp64_aos_{N}_rows", "rows": N, "p": 10, "bytes_per_row": 80,
                      "cache_flushed_between_steps": flush is not None,
                      "step": "reset + accumulate + finalize (cov, corr, PCA)"})
-    out["roofline"] = roof
+    out["roofline"] = add_measured_read(roof, L, [x.data_ptr()], [N * 80], stream)
     out["eigval_top3"] = [float(v) for v in fin["eigval"][:3]]
     return out
 
@@ -392,8 +405,9 @@ def run_groups(args, L, torch, datagen):
                      "step": "all waves: segmented accumulate (graph replay) + sync; generation and the warmup wave (autotune, graph capture) untimed"})
     out["steps"] = 1
     out["warmup"] = min(args.warmup, 1)
-    out["roofline"] = hbm_roofline("k_seg_aos64 + k_seg_merge (graph)", total * 256, kms, n1 - n0,
-                                   total * 256 / max(n1 - n0, 1))
+    out["roofline"] = add_measured_read(
+        hbm_roofline("k_seg_aos64 + k_seg_merge (graph)", total * 256, kms, n1 - n0,
+                     total * 256 / max(n1 - n0, 1)), L, [buf.data_ptr()], [wave_rows * 256], stream)
     out["finalize_groups_ms"] = round(1e3 * (tf1 - tf0), 1)
     out["identifier_closed_forms"] = f"{G - bad}/{G} groups exact"
     out["generation_s_untimed"] = round(gen_s, 2)
@@ -464,8 +478,10 @@ def run_text(args, L, torch, datagen):
                     {"workload": f"table1_csv_{N}_lines_1GiB_chunks", "rows": N, "p": 10,
                      "text_bytes": nbytes, "step": "reset + parse/accumulate all chunks + finalize"})
     out["text_gbs"] = round(nbytes / el / 1e9, 2)
-    out["roofline"] = hbm_roofline("k_text (parse fused with colsum + X^T X)", nbytes * args.steps,
-                                   ms1 - ms0, n1 - n0, nbytes * args.steps / max(n1 - n0, 1))
+    out["roofline"] = add_measured_read(
+        hbm_roofline("k_text (parse fused with colsum + X^T X)", nbytes * args.steps,
+                     ms1 - ms0, n1 - n0, nbytes * args.steps / max(n1 - n0, 1)),
+        L, [base], [nbytes], stream)
     return out
 
 

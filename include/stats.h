@@ -214,6 +214,18 @@ enum { STATS_K_ACCUM = 0, STATS_K_MERGE = 1, STATS_K_FINALIZE = 2, STATS_K_SYRK 
        STATS_K_SEGMENTED = 4, STATS_K_TEXT = 5, STATS_K_COPY = 6, STATS_K_COUNT = 7 };
 int stats_kernel_time(stats_ctx* h, int32_t which, int64_t* launches, double* total_ms);
 
+/* Measured read bandwidth (a measurement aid, not part of the statistics):
+ * the second denominator, beside the 8 TB/s HBM specification, for the
+ * achieved bandwidth of the reduction kernels.  For each of the n device
+ * buffers one kernel reads its nbytes[k] / 16 whole 16-byte vectors once
+ * (non-temporal loads; a tail below 16 bytes is not read) and discards them.
+ * bufs[k]: device address, 16-byte aligned unless nbytes[k] < 16.  Work is
+ * ordered on `stream` (hipStream_t, NULL = default stream); the call waits
+ * for it and stores the summed kernel time in ms into *ms_out (HIP events).
+ * Errors: STATS_E_ARG (NULL, negative or unaligned arguments), STATS_E_HIP. */
+int stats_read_probe(const void* const* bufs, const int64_t* nbytes, int32_t n, void* stream,
+                     double* ms_out);
+
 /* Releases the handle (NULL-safe; waits for its work first). */
 void stats_close(stats_ctx* h);
 

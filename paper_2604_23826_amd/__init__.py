@@ -88,6 +88,7 @@ _sig = {
     "stats_serialize": [_vp, _vp, ctypes.POINTER(ctypes.c_size_t)],
     "stats_deserialize": [_vp, ctypes.c_size_t, ctypes.POINTER(Config), ctypes.POINTER(_vp)],
     "stats_kernel_time": [_vp, _i32, ctypes.POINTER(_i64), ctypes.POINTER(ctypes.c_double)],
+    "stats_read_probe": [_vp, _vp, _i32, _vp, ctypes.POINTER(ctypes.c_double)],
 }
 for _name, _args in _sig.items():
     _f = getattr(_lib, _name)
@@ -291,6 +292,16 @@ def stats_kernel_time(h: int, which: int):
     ms = ctypes.c_double(0)
     _check(_lib.stats_kernel_time(h, which, ctypes.byref(n), ctypes.byref(ms)))
     return n.value, ms.value
+
+
+def stats_read_probe(bufs, nbytes, stream=None) -> float:
+    """Milliseconds to read the given device buffers once (see stats.h)."""
+    n = len(bufs)
+    b = (ctypes.c_void_p * max(n, 1))(*[_ptr(x) for x in bufs])
+    nb = (ctypes.c_int64 * max(n, 1))(*[int(x) for x in nbytes])
+    ms = ctypes.c_double(0)
+    _check(_lib.stats_read_probe(b, nb, n, stream or 0, ctypes.byref(ms)))
+    return ms.value
 
 
 def stats_close(h: int) -> None:

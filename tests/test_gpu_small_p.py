@@ -276,3 +276,20 @@ def test_table2_to_table3_on_gpu_eigensolver():
         assert np.max(np.abs(s * fin["eigvec"][k] - t3["loadings"][k])) <= 5.1e-7
     lam, vec = oracle.eig_sym(A)
     assert np.max(np.abs(fin["eigval"] - lam)) <= 1e-14
+
+
+def test_read_probe_times_reads_and_checks_arguments():
+    """The measurement aid behind the second bandwidth denominator: it times
+    a read of the given buffers and rejects unaligned or negative input."""
+    import torch
+    L = lib()
+    a = torch.zeros(1 << 24, dtype=torch.float64, device="cuda:0")
+    b = torch.zeros(1000, dtype=torch.int32, device="cuda:0")
+    ms = L.stats_read_probe([a.data_ptr(), b.data_ptr()], [a.numel() * 8, b.numel() * 4],
+                            current_stream())
+    assert ms > 0.0
+    assert L.stats_read_probe([], [], current_stream()) == 0.0
+    for bufs, sizes in (([a.data_ptr() + 4], [1024]), ([a.data_ptr()], [-1])):
+        with pytest.raises(L.StatsError) as e:
+            L.stats_read_probe(bufs, sizes, current_stream())
+        assert e.value.code == L.STATS_E_ARG
