@@ -26,7 +26,8 @@ namespace {
 
 constexpr int kThreads = 1024;
 constexpr int kLdsQ = 60;  // A and V in LDS up to this size (2 q^2 doubles <= 57.6 KiB)
-constexpr int kNB = 4;     // 2 x 2 blocks per thread and batch (global-memory case)
+constexpr int kNB = 4;     // 2 x 2 blocks per thread and batch
+constexpr int kNV = 4;     // V row pairs per thread and batch
 
 struct Args {
   const uint64_t* state;
@@ -76,13 +77,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   __shared__ int s_rot;
   const int m = q + (q & 1);  // players (a dummy when q is odd)
   const int npairs = m / 2;
-  extern __shared__ double s_dyn[];  // c[npairs], s[npairs], t[npairs], apq[npairs], A, V
+  // c[npairs], s[npairs], t[npairs], apq[npairs], the round's pairs, A, V
+  extern __shared__ double s_dyn[];
   double* rc = s_dyn;
   double* rs = rc + npairs;
   double* rt = rs + npairs;
   double* rapq = rt + npairs;
+  int2* rpair = (int2*)(rapq + npairs);
   double* A = f.scratch;
-  if (f.lds_mat) A = s_dyn + 4 * npairs;
+  if (f.lds_mat) A = s_dyn + 5 * npairs;
   double* V = A + (int64_t)q * q;
 
   // ---- means and covariance ----
@@ -165,46 +168,57 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
         rs[k] = s;
         rt[k] = t;
         rapq[k] = apq;
+        rpair[k] = make_int2(a, b);
       }
       __syncthreads();
       // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns); the blocks
-      // of a round are disjoint, so a batch is loaded before it is written
+      // of a round are disjoint, so a batch is loaded before it is written.
+      // Entry idx = u * npairs + v; (u, v) advance by nth without division.
       const int nblk = npairs * npairs;
+      const int du = nth / npairs, dv = nth % npairs;
+      int cu = tid / npairs, cv = tid % npairs;
       for (int base = tid; base < nblk; base += nth * kNB) {
         double x[kNB][4];
+        int ia[kNB], ib[kNB], ic[kNB], id[kNB], iu[kNB], iv[kNB];
 #pragma unroll
         for (int e = 0; e < kNB; ++e) {
-          const int idx = base + e * nth;
+          iu[e] = cu;
+          iv[e] = cv;
+          cv += dv;
+          cu += du;
+          if (cv >= npairs) {
+            cv -= npairs;
+            ++cu;
+          }
           x[e][0] = x[e][1] = x[e][2] = x[e][3] = 0.0;
-          if (idx >= nblk) continue;
-          const int u = idx / npairs, v = idx % npairs;
-          int a, b, c2, d2;
-          rr_pair(u, r, m, a, b);
-          rr_pair(v, r, m, c2, d2);
-          const bool bq = b < q, dq = d2 < q;
-          x[e][0] = A[(int64_t)a * q + c2];
-          if (dq) x[e][1] = A[(int64_t)a * q + d2];
-          if (bq) x[e][2] = A[(int64_t)b * q + c2];
-          if (bq && dq) x[e][3] = A[(int64_t)b * q + d2];
+          ia[e] = ib[e] = ic[e] = id[e] = 0;
+          if (base + e * nth >= nblk) continue;
+          const int2 pu = rpair[iu[e]], pv = rpair[iv[e]];
+          ia[e] = pu.x;
+          ib[e] = pu.y;
+          ic[e] = pv.x;
+          id[e] = pv.y;
+          const bool bq = ib[e] < q, dq = id[e] < q;
+          x[e][0] = A[(int64_t)ia[e] * q + ic[e]];
+          if (dq) x[e][1] = A[(int64_t)ia[e] * q + id[e]];
+          if (bq) x[e][2] = A[(int64_t)ib[e] * q + ic[e]];
+          if (bq && dq) x[e][3] = A[(int64_t)ib[e] * q + id[e]];
         }
 #pragma unroll
         for (int e = 0; e < kNB; ++e) {
-          const int idx = base + e * nth;
-          if (idx >= nblk) continue;
-          const int u = idx / npairs, v = idx % npairs;
-          const double cu = rc[u], su = rs[u], cv = rc[v], sv = rs[v];
+          if (base + e * nth >= nblk) continue;
+          const int u = iu[e], v = iv[e];
+          const double cu_ = rc[u], su = rs[u], cv_ = rc[v], sv = rs[v];
           if (su == 0.0 && sv == 0.0) continue;
-          int a, b, c2, d2;
-          rr_pair(u, r, m, a, b);
-          rr_pair(v, r, m, c2, d2);
+          const int a = ia[e], b = ib[e], c2 = ic[e], d2 = id[e];
           const bool bq = b < q, dq = d2 < q;
           const double x00 = x[e][0], x01 = x[e][1], x10 = x[e][2], x11 = x[e][3];
           // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
-          const double y00 = cu * x00 - su * x10, y10 = su * x00 + cu * x10;
-          const double y01 = cu * x01 - su * x11, y11 = su * x01 + cu * x11;
+          const double y00 = cu_ * x00 - su * x10, y10 = su * x00 + cu_ * x10;
+          const double y01 = cu_ * x01 - su * x11, y11 = su * x01 + cu_ * x11;
           // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
-          double z00 = cv * y00 - sv * y01, z01 = sv * y00 + cv * y01;
-          double z10 = cv * y10 - sv * y11, z11 = sv * y10 + cv * y11;
+          double z00 = cv_ * y00 - sv * y01, z01 = sv * y00 + cv_ * y01;
+          double z10 = cv_ * y10 - sv * y11, z11 = sv * y10 + cv_ * y11;
           if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
             const double t = rt[u], apq = rapq[u];
             z00 = x00 - t * apq;
@@ -218,18 +232,40 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
           if (bq && dq) A[(int64_t)b * q + d2] = z11;
         }
       }
-      // V <- V J
-      for (int idx = tid; idx < q * npairs; idx += nth) {
-        const int row = idx / npairs, u = idx % npairs;
-        int a, b;
-        rr_pair(u, r, m, a, b);
-        if (b >= q) continue;  // the dummy player of odd q
-        const double va = V[(int64_t)row * q + a], vb = V[(int64_t)row * q + b];
-        const double s = rs[u];
-        if (s == 0.0) continue;
-        const double c = rc[u];
-        V[(int64_t)row * q + a] = c * va - s * vb;
-        V[(int64_t)row * q + b] = s * va + c * vb;
+      // V <- V J (entry idx = row * npairs + u), batched the same way
+      const int nv = q * npairs;
+      int vr = tid / npairs, vu = tid % npairs;
+      for (int base = tid; base < nv; base += nth * kNV) {
+        double va[kNV], vb[kNV];
+        int jr[kNV], ju[kNV];
+#pragma unroll
+        for (int e = 0; e < kNV; ++e) {
+          jr[e] = vr;
+          ju[e] = vu;
+          vu += dv;
+          vr += du;
+          if (vu >= npairs) {
+            vu -= npairs;
+            ++vr;
+          }
+          va[e] = vb[e] = 0.0;
+          if (base + e * nth >= nv) continue;
+          const int2 pu = rpair[ju[e]];
+          if (pu.y >= q) continue;  // the dummy player of odd q
+          va[e] = V[(int64_t)jr[e] * q + pu.x];
+          vb[e] = V[(int64_t)jr[e] * q + pu.y];
+        }
+#pragma unroll
+        for (int e = 0; e < kNV; ++e) {
+          if (base + e * nth >= nv) continue;
+          const int u = ju[e];
+          const double s = rs[u];
+          if (s == 0.0) continue;  // also the dummy player's pair
+          const int2 pu = rpair[u];
+          const double c = rc[u];
+          V[(int64_t)jr[e] * q + pu.x] = c * va[e] - s * vb[e];
+          V[(int64_t)jr[e] * q + pu.y] = s * va[e] + c * vb[e];
+        }
       }
       __syncthreads();
     }
@@ -329,7 +365,7 @@ void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
   a.out = F.out;
   a.scratch = F.scratch;
   const int npairs = (F.q + (F.q & 1)) / 2;
-  size_t shm = (size_t)npairs * 4 * sizeof(double);
+  size_t shm = (size_t)npairs * 5 * sizeof(double);
   a.lds_mat = F.q <= kLdsQ;
   if (a.lds_mat) shm += 2 * sizeof(double) * (size_t)F.q * F.q;
   // one wave for the small matrices of the narrow path (its barriers cost
