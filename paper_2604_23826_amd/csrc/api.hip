@@ -685,7 +685,8 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   const int q = (int)sel.size();
   const size_t out_words = (size_t)q * 4 + 3 * (size_t)q * q;
   rc = ensure_dev(h, (void**)&h->fin_out, &h->fin_out_cap, out_words * 8);
-  if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, 2 * (size_t)q * q * 8);
+  const size_t jtab_words = 5 * (size_t)((q + 1) / 2);
+  if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, (2 * (size_t)q * q + jtab_words + 1) * 8);
   if (!rc) rc = ensure_dev(h, (void**)&h->sel_dev, &h->sel_cap, (size_t)q * 4);
   if (rc) return rc;
   e = hipMemcpyAsync(h->sel_dev, sel.data(), (size_t)q * 4, hipMemcpyHostToDevice, h->stream);
@@ -701,14 +702,15 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   F.want_vectors = 1;
   F.out = h->fin_out;
   F.scratch = h->fin_scratch;
+  F.jtab = h->fin_scratch + 2 * (size_t)q * q;
+  F.jc = (unsigned*)(F.jtab + jtab_words);
   {
     Timer t;
     t.begin(h, STATS_K_FINALIZE);
-    launch_finalize(F, h->stream);
+    e = launch_finalize(F, h->stream);
     t.end();
   }
-  e = hipGetLastError();
-  if (e != hipSuccess) return hip_fail(h, e, "finalize kernel launch");
+  if (e != hipSuccess) return hip_fail(h, e, "finalize");
   std::vector<double> out(out_words);
   e = hipMemcpyAsync(out.data(), h->fin_out, out_words * 8, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);

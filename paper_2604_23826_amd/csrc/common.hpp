@@ -408,8 +408,12 @@ struct FinalizeLaunch {
   int want_vectors;
   double* out;      // mean q, cov q*q, corr q*q, eigval q, eigvec q*q, var q, cum q
   double* scratch;  // 2 q*q (Jacobi A and V)
+  double* jtab;     // q > 60: 5 * ceil(q / 2) (rotation tables of a round)
+  unsigned* jc;     // q > 60: 2 words (rotation count, non-finite flag)
 };
-void launch_finalize(const FinalizeLaunch& f, hipStream_t s);
+// Enqueues the finalize kernels on s.  Matrices above 60 x 60 run one kernel
+// pair per Jacobi round and wait on s after every sweep.
+hipError_t launch_finalize(const FinalizeLaunch& f, hipStream_t s);
 
 // Raw statistics as FP64: s_f64[p], C_f64[p*p] (full) from a state.
 void launch_raw(const uint64_t* state, int p, const uint8_t* intflags_dev, double* out,

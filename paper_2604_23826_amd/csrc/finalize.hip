@@ -28,6 +28,8 @@ constexpr int kThreads = 1024;
 constexpr int kLdsQ = 60;  // A and V in LDS up to this size (2 q^2 doubles <= 57.6 KiB)
 constexpr int kNB = 4;     // 2 x 2 blocks per thread and batch
 constexpr int kNV = 4;     // V row pairs per thread and batch
+constexpr int kMaxSweeps = 60;
+constexpr int kJThreads = 256;  // workgroup of the multi-kernel rounds
 
 struct Args {
   const uint64_t* state;
@@ -41,7 +43,11 @@ struct Args {
   double* out;
   double* scratch;
   int lds_mat;  // A and V in dynamic LDS after the rotation tables
+  int phase;     // kAll, or kPre / kPost around the multi-kernel Jacobi
+  unsigned* jc;  // kPre / kPost: [0] rotations of a sweep, [1] non-finite input
 };
+
+enum { kAll = 0, kPre = 1, kPost = 2 };
 
 // Round-robin schedule on m (even) players: player at position pos in round
 // r (0 <= pos < m, 0 <= r < m - 1).
@@ -56,6 +62,143 @@ __device__ inline void rr_pair(int k, int r, int m, int& a, int& b) {
   const int x = rr_player(k, r, m), y = rr_player(m - 1 - k, r, m);
   a = min(x, y);
   b = max(x, y);
+}
+
+// Rotation tables of one round: cosine, sine, tangent, the annihilated
+// element and the pair (a, b) of every pair k.
+struct RotTab {
+  double* c;
+  double* s;
+  double* t;
+  double* apq;
+  int2* pair;
+  __device__ static RotTab at(double* base, int npairs) {
+    return RotTab{base, base + npairs, base + 2 * npairs, base + 3 * npairs, (int2*)(base + 4 * npairs)};
+  }
+};
+
+// Jacobi rotation annihilating A[a][b] (a < b < q), or none (c = 1, s = 0)
+// when the element is already negligible.  Returns whether it rotates.
+__device__ inline bool jacobi_rotation(const double* A, int q, int a, int b, double& c, double& s, double& t,
+                                       double& apq) {
+  const double tol = 2.220446049250313e-16;
+  c = 1.0;
+  s = t = 0.0;
+  apq = A[(int64_t)a * q + b];
+  const double app = A[(int64_t)a * q + a], aqq = A[(int64_t)b * q + b];
+  if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+    const double theta = (aqq - app) / (2.0 * apq);
+    t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
+    c = 1.0 / sqrt(t * t + 1.0);
+    s = t * c;
+    return true;
+  }
+  apq = 0.0;
+  return false;
+}
+
+// A <- J^T A J on the 2x2 blocks idx = u * npairs + v of one round (pair u
+// rows, pair v columns), idx = start, start + stride, ...  The blocks of a
+// round are disjoint, so a batch is loaded before it is written; (u, v)
+// advance by stride without division.
+__device__ inline void jacobi_blocks(double* A, int q, int npairs, const RotTab& R, int start, int stride) {
+  const int nblk = npairs * npairs;
+  const int du = stride / npairs, dv = stride % npairs;
+  int cu = start / npairs, cv = start % npairs;
+  for (int base = start; base < nblk; base += stride * kNB) {
+    double x[kNB][4];
+    int ia[kNB], ib[kNB], ic[kNB], id[kNB], iu[kNB], iv[kNB];
+#pragma unroll
+    for (int e = 0; e < kNB; ++e) {
+      iu[e] = cu;
+      iv[e] = cv;
+      cv += dv;
+      cu += du;
+      if (cv >= npairs) {
+        cv -= npairs;
+        ++cu;
+      }
+      x[e][0] = x[e][1] = x[e][2] = x[e][3] = 0.0;
+      ia[e] = ib[e] = ic[e] = id[e] = 0;
+      if (base + e * stride >= nblk) continue;
+      const int2 pu = R.pair[iu[e]], pv = R.pair[iv[e]];
+      ia[e] = pu.x;
+      ib[e] = pu.y;
+      ic[e] = pv.x;
+      id[e] = pv.y;
+      const bool bq = ib[e] < q, dq = id[e] < q;
+      x[e][0] = A[(int64_t)ia[e] * q + ic[e]];
+      if (dq) x[e][1] = A[(int64_t)ia[e] * q + id[e]];
+      if (bq) x[e][2] = A[(int64_t)ib[e] * q + ic[e]];
+      if (bq && dq) x[e][3] = A[(int64_t)ib[e] * q + id[e]];
+    }
+#pragma unroll
+    for (int e = 0; e < kNB; ++e) {
+      if (base + e * stride >= nblk) continue;
+      const int u = iu[e], v = iv[e];
+      const double cu_ = R.c[u], su = R.s[u], cv_ = R.c[v], sv = R.s[v];
+      if (su == 0.0 && sv == 0.0) continue;
+      const int a = ia[e], b = ib[e], c2 = ic[e], d2 = id[e];
+      const bool bq = b < q, dq = d2 < q;
+      const double x00 = x[e][0], x01 = x[e][1], x10 = x[e][2], x11 = x[e][3];
+      // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
+      const double y00 = cu_ * x00 - su * x10, y10 = su * x00 + cu_ * x10;
+      const double y01 = cu_ * x01 - su * x11, y11 = su * x01 + cu_ * x11;
+      // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
+      double z00 = cv_ * y00 - sv * y01, z01 = sv * y00 + cv_ * y01;
+      double z10 = cv_ * y10 - sv * y11, z11 = sv * y10 + cv_ * y11;
+      if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
+        const double t = R.t[u], apq = R.apq[u];
+        z00 = x00 - t * apq;
+        z11 = x11 + t * apq;
+        z01 = 0.0;
+        z10 = 0.0;
+      }
+      A[(int64_t)a * q + c2] = z00;
+      if (dq) A[(int64_t)a * q + d2] = z01;
+      if (bq) A[(int64_t)b * q + c2] = z10;
+      if (bq && dq) A[(int64_t)b * q + d2] = z11;
+    }
+  }
+}
+
+// V <- V J on the entries idx = row * npairs + u, batched the same way.
+__device__ inline void jacobi_vectors(double* V, int q, int npairs, const RotTab& R, int start, int stride) {
+  const int nv = q * npairs;
+  const int du = stride / npairs, dv = stride % npairs;
+  int vr = start / npairs, vu = start % npairs;
+  for (int base = start; base < nv; base += stride * kNV) {
+    double va[kNV], vb[kNV];
+    int jr[kNV], ju[kNV];
+#pragma unroll
+    for (int e = 0; e < kNV; ++e) {
+      jr[e] = vr;
+      ju[e] = vu;
+      vu += dv;
+      vr += du;
+      if (vu >= npairs) {
+        vu -= npairs;
+        ++vr;
+      }
+      va[e] = vb[e] = 0.0;
+      if (base + e * stride >= nv) continue;
+      const int2 pu = R.pair[ju[e]];
+      if (pu.y >= q) continue;  // the dummy player of odd q
+      va[e] = V[(int64_t)jr[e] * q + pu.x];
+      vb[e] = V[(int64_t)jr[e] * q + pu.y];
+    }
+#pragma unroll
+    for (int e = 0; e < kNV; ++e) {
+      if (base + e * stride >= nv) continue;
+      const int u = ju[e];
+      const double s = R.s[u];
+      if (s == 0.0) continue;  // also the dummy player's pair
+      const int2 pu = R.pair[u];
+      const double c = R.c[u];
+      V[(int64_t)jr[e] * q + pu.x] = c * va[e] - s * vb[e];
+      V[(int64_t)jr[e] * q + pu.y] = s * va[e] + c * vb[e];
+    }
+  }
 }
 
 __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
@@ -79,15 +222,16 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   const int npairs = m / 2;
   // c[npairs], s[npairs], t[npairs], apq[npairs], the round's pairs, A, V
   extern __shared__ double s_dyn[];
-  double* rc = s_dyn;
-  double* rs = rc + npairs;
-  double* rt = rs + npairs;
-  double* rapq = rt + npairs;
-  int2* rpair = (int2*)(rapq + npairs);
+  const RotTab R = RotTab::at(s_dyn, npairs);
   double* A = f.scratch;
   if (f.lds_mat) A = s_dyn + 5 * npairs;
   double* V = A + (int64_t)q * q;
 
+  if (f.phase == kPost) {
+    if (f.jc[1]) return;  // non-finite input: the pre phase wrote NaN
+    goto sort_and_sign;
+  }
+  {
   // ---- means and covariance ----
   const double dn = (double)(n - f.ddof);
   for (int a = tid; a < q; a += nth) {
@@ -132,6 +276,10 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   }
   if (bad) atomicOr(&s_flag, 1);
   __syncthreads();
+  if (f.phase == kPre && tid == 0) {
+    f.jc[0] = 0;
+    f.jc[1] = s_flag ? 1u : 0u;
+  }
   if (s_flag) {
     for (int idx = tid; idx < qq; idx += nth) evec[idx] = __builtin_nan("");
     for (int a = tid; a < q; a += nth) {
@@ -139,140 +287,35 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     }
     return;
   }
+  if (f.phase == kPre) return;
 
-  // ---- cyclic Jacobi, round-robin ordering ----
-  const double tol = 2.220446049250313e-16;
-  for (int sweep = 0; sweep < 60 && q > 1; ++sweep) {
+  // ---- cyclic Jacobi, round-robin ordering: q/2 disjoint rotations per round ----
+  for (int sweep = 0; sweep < kMaxSweeps && q > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
     for (int r = 0; r < m - 1; ++r) {
-      // rotations of this round (one thread per disjoint pair)
       for (int k = tid; k < npairs; k += nth) {
         int a, b;
         rr_pair(k, r, m, a, b);
         double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
-        if (b < q) {
-          apq = A[(int64_t)a * q + b];
-          const double app = A[(int64_t)a * q + a], aqq = A[(int64_t)b * q + b];
-          if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
-            const double theta = (aqq - app) / (2.0 * apq);
-            t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
-            c = 1.0 / sqrt(t * t + 1.0);
-            s = t * c;
-            atomicAdd(&s_rot, 1);
-          } else {
-            apq = 0.0;
-          }
-        }
-        rc[k] = c;
-        rs[k] = s;
-        rt[k] = t;
-        rapq[k] = apq;
-        rpair[k] = make_int2(a, b);
+        if (b < q && jacobi_rotation(A, q, a, b, c, s, t, apq)) atomicAdd(&s_rot, 1);
+        R.c[k] = c;
+        R.s[k] = s;
+        R.t[k] = t;
+        R.apq[k] = apq;
+        R.pair[k] = make_int2(a, b);
       }
       __syncthreads();
-      // A <- J^T A J on 2x2 blocks (pair u rows, pair v columns); the blocks
-      // of a round are disjoint, so a batch is loaded before it is written.
-      // Entry idx = u * npairs + v; (u, v) advance by nth without division.
-      const int nblk = npairs * npairs;
-      const int du = nth / npairs, dv = nth % npairs;
-      int cu = tid / npairs, cv = tid % npairs;
-      for (int base = tid; base < nblk; base += nth * kNB) {
-        double x[kNB][4];
-        int ia[kNB], ib[kNB], ic[kNB], id[kNB], iu[kNB], iv[kNB];
-#pragma unroll
-        for (int e = 0; e < kNB; ++e) {
-          iu[e] = cu;
-          iv[e] = cv;
-          cv += dv;
-          cu += du;
-          if (cv >= npairs) {
-            cv -= npairs;
-            ++cu;
-          }
-          x[e][0] = x[e][1] = x[e][2] = x[e][3] = 0.0;
-          ia[e] = ib[e] = ic[e] = id[e] = 0;
-          if (base + e * nth >= nblk) continue;
-          const int2 pu = rpair[iu[e]], pv = rpair[iv[e]];
-          ia[e] = pu.x;
-          ib[e] = pu.y;
-          ic[e] = pv.x;
-          id[e] = pv.y;
-          const bool bq = ib[e] < q, dq = id[e] < q;
-          x[e][0] = A[(int64_t)ia[e] * q + ic[e]];
-          if (dq) x[e][1] = A[(int64_t)ia[e] * q + id[e]];
-          if (bq) x[e][2] = A[(int64_t)ib[e] * q + ic[e]];
-          if (bq && dq) x[e][3] = A[(int64_t)ib[e] * q + id[e]];
-        }
-#pragma unroll
-        for (int e = 0; e < kNB; ++e) {
-          if (base + e * nth >= nblk) continue;
-          const int u = iu[e], v = iv[e];
-          const double cu_ = rc[u], su = rs[u], cv_ = rc[v], sv = rs[v];
-          if (su == 0.0 && sv == 0.0) continue;
-          const int a = ia[e], b = ib[e], c2 = ic[e], d2 = id[e];
-          const bool bq = b < q, dq = d2 < q;
-          const double x00 = x[e][0], x01 = x[e][1], x10 = x[e][2], x11 = x[e][3];
-          // rows: (row a, row b) <- (c row a - s row b, s row a + c row b)
-          const double y00 = cu_ * x00 - su * x10, y10 = su * x00 + cu_ * x10;
-          const double y01 = cu_ * x01 - su * x11, y11 = su * x01 + cu_ * x11;
-          // columns: (col c2, col d2) <- (c col c2 - s col d2, s col c2 + c col d2)
-          double z00 = cv_ * y00 - sv * y01, z01 = sv * y00 + cv_ * y01;
-          double z10 = cv_ * y10 - sv * y11, z11 = sv * y10 + cv_ * y11;
-          if (u == v && su != 0.0) {  // the rotated 2x2 block itself: exact update
-            const double t = rt[u], apq = rapq[u];
-            z00 = x00 - t * apq;
-            z11 = x11 + t * apq;
-            z01 = 0.0;
-            z10 = 0.0;
-          }
-          A[(int64_t)a * q + c2] = z00;
-          if (dq) A[(int64_t)a * q + d2] = z01;
-          if (bq) A[(int64_t)b * q + c2] = z10;
-          if (bq && dq) A[(int64_t)b * q + d2] = z11;
-        }
-      }
-      // V <- V J (entry idx = row * npairs + u), batched the same way
-      const int nv = q * npairs;
-      int vr = tid / npairs, vu = tid % npairs;
-      for (int base = tid; base < nv; base += nth * kNV) {
-        double va[kNV], vb[kNV];
-        int jr[kNV], ju[kNV];
-#pragma unroll
-        for (int e = 0; e < kNV; ++e) {
-          jr[e] = vr;
-          ju[e] = vu;
-          vu += dv;
-          vr += du;
-          if (vu >= npairs) {
-            vu -= npairs;
-            ++vr;
-          }
-          va[e] = vb[e] = 0.0;
-          if (base + e * nth >= nv) continue;
-          const int2 pu = rpair[ju[e]];
-          if (pu.y >= q) continue;  // the dummy player of odd q
-          va[e] = V[(int64_t)jr[e] * q + pu.x];
-          vb[e] = V[(int64_t)jr[e] * q + pu.y];
-        }
-#pragma unroll
-        for (int e = 0; e < kNV; ++e) {
-          if (base + e * nth >= nv) continue;
-          const int u = ju[e];
-          const double s = rs[u];
-          if (s == 0.0) continue;  // also the dummy player's pair
-          const int2 pu = rpair[u];
-          const double c = rc[u];
-          V[(int64_t)jr[e] * q + pu.x] = c * va[e] - s * vb[e];
-          V[(int64_t)jr[e] * q + pu.y] = s * va[e] + c * vb[e];
-        }
-      }
+      jacobi_blocks(A, q, npairs, R, tid, nth);
+      jacobi_vectors(V, q, npairs, R, tid, nth);
       __syncthreads();
     }
     if (s_rot == 0) break;
     __syncthreads();
   }
+  }
 
+sort_and_sign:
   // ---- sort descending (ties: lower index first), sign rule, percentages ----
   for (int k = tid; k < q; k += nth) {
     const double lk = A[(int64_t)k * q + k];
@@ -307,6 +350,40 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
       cump[k] = run;
     }
   }
+}
+
+// Multi-kernel Jacobi for q > kLdsQ (A and V in global memory): one round is
+// k_jrot (one workgroup: the round's rotation tables, and the count of
+// rotations) followed by k_japply (the 2x2 blocks of A and the rows of V,
+// spread over many workgroups).  Same arithmetic as the one-workgroup loop.
+__global__ __launch_bounds__(kThreads) void k_jrot(const double* __restrict__ A, int q, int m, int r,
+                                                   double* tab, unsigned* jc) {
+  const int npairs = m / 2;
+  const RotTab R = RotTab::at(tab, npairs);
+  unsigned cnt = 0;
+  for (int k = threadIdx.x; k < npairs; k += blockDim.x) {
+    int a, b;
+    rr_pair(k, r, m, a, b);
+    double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
+    if (b < q && jacobi_rotation(A, q, a, b, c, s, t, apq)) ++cnt;
+    R.c[k] = c;
+    R.s[k] = s;
+    R.t[k] = t;
+    R.apq[k] = apq;
+    R.pair[k] = make_int2(a, b);
+  }
+  if (cnt) atomicAdd(&jc[0], cnt);
+}
+
+__global__ __launch_bounds__(kJThreads) void k_japply(double* A, double* V, int q, int m, const double* tab) {
+  const int npairs = m / 2;
+  extern __shared__ double s_tab[];  // the round's tables, copied once
+  for (int i = threadIdx.x; i < 5 * npairs; i += kJThreads) s_tab[i] = tab[i];
+  __syncthreads();
+  const RotTab R = RotTab::at(s_tab, npairs);
+  const int start = blockIdx.x * kJThreads + threadIdx.x, stride = gridDim.x * kJThreads;
+  jacobi_blocks(A, q, npairs, R, start, stride);
+  jacobi_vectors(V, q, npairs, R, start, stride);
 }
 
 __global__ void k_raw(const uint64_t* st, int p, const uint8_t* intf, double* out) {
@@ -352,7 +429,7 @@ __global__ void k_raw(const uint64_t* st, int p, const uint8_t* intf, double* ou
 
 }  // namespace
 
-void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
+hipError_t launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
   Args a;
   a.state = F.state;
   a.p = F.p;
@@ -364,14 +441,48 @@ void launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
   a.want_vectors = F.want_vectors;
   a.out = F.out;
   a.scratch = F.scratch;
+  a.jc = F.jc;
   const int npairs = (F.q + (F.q & 1)) / 2;
   size_t shm = (size_t)npairs * 5 * sizeof(double);
   a.lds_mat = F.q <= kLdsQ;
-  if (a.lds_mat) shm += 2 * sizeof(double) * (size_t)F.q * F.q;
-  // one wave for the small matrices of the narrow path (its barriers cost
-  // nothing), more threads for wide ones
-  const int nth = F.q <= 16 ? 64 : F.q <= kLdsQ ? 256 : kThreads;
-  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(nth), shm, s, a);
+  if (a.lds_mat) {
+    // one workgroup does everything; one wave for the small matrices of the
+    // narrow path (its barriers cost nothing)
+    shm += 2 * sizeof(double) * (size_t)F.q * F.q;
+    a.phase = kAll;
+    hipLaunchKernelGGL(k_finalize, dim3(1), dim3(F.q <= 16 ? 64 : 256), shm, s, a);
+    return hipGetLastError();
+  }
+  // wide matrices: the Jacobi rounds as separate kernels over the whole GPU,
+  // sweeps until one makes no rotation
+  a.phase = kPre;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), shm, s, a);
+  hipError_t e = hipGetLastError();
+  double* A = F.scratch;
+  double* V = A + (int64_t)F.q * F.q;
+  const int m = 2 * npairs;
+  int dev = 0, ncu = 256;
+  if (e == hipSuccess) e = hipGetDevice(&dev);
+  if (e == hipSuccess) e = hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, dev);
+  const int64_t work = (int64_t)npairs * npairs + (int64_t)F.q * npairs;
+  const int nwg = (int)std::max<int64_t>(1, std::min<int64_t>((work + kJThreads * kNB - 1) / (kJThreads * kNB), 4 * ncu));
+  const size_t tab_shm = (size_t)npairs * 5 * sizeof(double);
+  for (int sweep = 0; sweep < kMaxSweeps && F.q > 1 && e == hipSuccess; ++sweep) {
+    e = hipMemsetAsync(F.jc, 0, sizeof(unsigned), s);
+    for (int r = 0; r < m - 1 && e == hipSuccess; ++r) {
+      hipLaunchKernelGGL(k_jrot, dim3(1), dim3(kThreads), 0, s, A, F.q, m, r, F.jtab, F.jc);
+      hipLaunchKernelGGL(k_japply, dim3(nwg), dim3(kJThreads), tab_shm, s, A, V, F.q, m, F.jtab);
+      e = hipGetLastError();
+    }
+    unsigned rot = 0;
+    if (e == hipSuccess) e = hipMemcpyAsync(&rot, F.jc, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    if (e == hipSuccess) e = hipStreamSynchronize(s);
+    if (e != hipSuccess || rot == 0) break;
+  }
+  if (e != hipSuccess) return e;
+  a.phase = kPost;
+  hipLaunchKernelGGL(k_finalize, dim3(1), dim3(kThreads), shm, s, a);
+  return hipGetLastError();
 }
 
 void launch_raw(const uint64_t* state, int p, const uint8_t* intf, double* out, hipStream_t s) {
