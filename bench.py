@@ -507,7 +507,7 @@ def main():
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:
-        print("bench.py measures one GPU only: this build runs on a single MI355X "
+        print("bench.py measures one GPU only: the library runs on a single MI355X "
               "(the multi-GPU split of the rows is a design note, not built); use --gpus 1",
               file=sys.stderr)
         sys.exit(2)
