@@ -290,6 +290,94 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   if (f.phase == kPre) return;
 
   // ---- cyclic Jacobi, round-robin ordering: q/2 disjoint rotations per round ----
+  if (nth == 64 && q <= 16) {
+    // One wave, at most one 2x2 block and two V row pairs per lane.  Each
+    // round issues all of its loads (block, V pairs, rotation inputs) right
+    // after the barrier, with the pair indices computed, not looked up; the
+    // rotation tables are read once, after the second barrier.  The same
+    // arithmetic as jacobi_blocks / jacobi_vectors.
+    const int nblk = npairs * npairs, nv = q * npairs;
+    const bool hasb = tid < nblk;
+    const int bu = tid / npairs, bv = tid % npairs;
+    int vrow[2], vu[2];
+    bool hasv[2];
+#pragma unroll
+    for (int j = 0; j < 2; ++j) {
+      const int idx = tid + 64 * j;
+      hasv[j] = idx < nv;
+      vrow[j] = idx / npairs;
+      vu[j] = idx % npairs;
+    }
+    for (int sweep = 0; sweep < kMaxSweeps && q > 1; ++sweep) {
+      if (tid == 0) s_rot = 0;
+      __syncthreads();
+      for (int r = 0; r < m - 1; ++r) {
+        int a = 0, b = 0, c2 = 0, d2 = 0;
+        double x00 = 0.0, x01 = 0.0, x10 = 0.0, x11 = 0.0;
+        if (hasb) {
+          rr_pair(bu, r, m, a, b);
+          rr_pair(bv, r, m, c2, d2);
+          x00 = A[a * q + c2];
+          if (d2 < q) x01 = A[a * q + d2];
+          if (b < q) x10 = A[b * q + c2];
+          if (b < q && d2 < q) x11 = A[b * q + d2];
+        }
+        int pa[2], pb[2];
+        double va[2] = {0.0, 0.0}, vb[2] = {0.0, 0.0};
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          rr_pair(vu[j], r, m, pa[j], pb[j]);
+          if (hasv[j] && pb[j] < q) {
+            va[j] = V[vrow[j] * q + pa[j]];
+            vb[j] = V[vrow[j] * q + pb[j]];
+          }
+        }
+        if (tid < npairs) {
+          int ra, rb;
+          rr_pair(tid, r, m, ra, rb);
+          double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
+          if (rb < q && jacobi_rotation(A, q, ra, rb, c, s, t, apq)) atomicAdd(&s_rot, 1);
+          R.c[tid] = c;
+          R.s[tid] = s;
+          R.t[tid] = t;
+          R.apq[tid] = apq;
+        }
+        __syncthreads();
+        if (hasb) {
+          const double cu_ = R.c[bu], su = R.s[bu], cv_ = R.c[bv], sv = R.s[bv];
+          if (su != 0.0 || sv != 0.0) {
+            const double y00 = cu_ * x00 - su * x10, y10 = su * x00 + cu_ * x10;
+            const double y01 = cu_ * x01 - su * x11, y11 = su * x01 + cu_ * x11;
+            double z00 = cv_ * y00 - sv * y01, z01 = sv * y00 + cv_ * y01;
+            double z10 = cv_ * y10 - sv * y11, z11 = sv * y10 + cv_ * y11;
+            if (bu == bv && su != 0.0) {  // the rotated 2x2 block itself: exact update
+              const double t = R.t[bu], apq = R.apq[bu];
+              z00 = x00 - t * apq;
+              z11 = x11 + t * apq;
+              z01 = 0.0;
+              z10 = 0.0;
+            }
+            A[a * q + c2] = z00;
+            if (d2 < q) A[a * q + d2] = z01;
+            if (b < q) A[b * q + c2] = z10;
+            if (b < q && d2 < q) A[b * q + d2] = z11;
+          }
+        }
+#pragma unroll
+        for (int j = 0; j < 2; ++j) {
+          if (!hasv[j] || pb[j] >= q) continue;
+          const double s = R.s[vu[j]];
+          if (s == 0.0) continue;
+          const double c = R.c[vu[j]];
+          V[vrow[j] * q + pa[j]] = c * va[j] - s * vb[j];
+          V[vrow[j] * q + pb[j]] = s * va[j] + c * vb[j];
+        }
+        __syncthreads();
+      }
+      if (s_rot == 0) break;
+      __syncthreads();
+    }
+  } else {
   for (int sweep = 0; sweep < kMaxSweeps && q > 1; ++sweep) {
     if (tid == 0) s_rot = 0;
     __syncthreads();
@@ -312,6 +400,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     }
     if (s_rot == 0) break;
     __syncthreads();
+  }
   }
   }
 
