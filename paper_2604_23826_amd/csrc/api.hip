@@ -323,10 +323,13 @@ static int layout_kind(const stats_ctx* h, const void* const* planes) {
 }
 
 static int64_t auto_block_rows(int64_t nrows) {
-  // target ~2048 blocks per launch, between 1024 rows and 2^17 rows per block
+  // target ~2048 blocks per launch, between 4096 rows and 2^17 rows per block;
+  // below 4096 rows per block the per-block reduction and pipeline start
+  // dominate (10^6 FP64 rows of 80 bytes: 22 us with 4096-row blocks, 31 us
+  // with 1024)
   int64_t R = (nrows + 2047) / 2048;
   R = ((R + 1023) / 1024) * 1024;
-  return std::max<int64_t>(1024, std::min<int64_t>(R, (int64_t)1 << 17));
+  return std::max<int64_t>(4096, std::min<int64_t>(R, (int64_t)1 << 17));
 }
 
 // Reduce nrows device-resident rows (plane bases already offset to the first
