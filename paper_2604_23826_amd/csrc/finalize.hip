@@ -77,16 +77,22 @@ struct RotTab {
   }
 };
 
+// Whether the element apq of the pair with diagonal entries app, aqq is
+// rotated away: not when it is already negligible against them.
+__device__ inline bool rotates(double apq, double app, double aqq) {
+  const double tol = 2.220446049250313e-16;
+  return apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq));
+}
+
 // Jacobi rotation annihilating A[a][b] (a < b < q), or none (c = 1, s = 0)
 // when the element is already negligible.  Returns whether it rotates.
 __device__ inline bool jacobi_rotation(const double* A, int q, int a, int b, double& c, double& s, double& t,
                                        double& apq) {
-  const double tol = 2.220446049250313e-16;
   c = 1.0;
   s = t = 0.0;
   apq = A[(int64_t)a * q + b];
   const double app = A[(int64_t)a * q + a], aqq = A[(int64_t)b * q + b];
-  if (apq != 0.0 && fabs(apq) > tol * sqrt(fabs(app * aqq))) {
+  if (rotates(apq, app, aqq)) {
     const double theta = (aqq - app) / (2.0 * apq);
     t = (theta >= 0.0 ? 1.0 : -1.0) / (fabs(theta) + sqrt(theta * theta + 1.0));
     c = 1.0 / sqrt(t * t + 1.0);
@@ -201,6 +207,22 @@ __device__ inline void jacobi_vectors(double* V, int q, int npairs, const RotTab
   }
 }
 
+// End of a sweep (after its last barrier): true when no pair would rotate,
+// i.e. the next sweep would change nothing, so stopping now gives the same
+// result one sweep earlier.  *cnt is workgroup-shared scratch (reset here).
+__device__ inline bool converged(const double* A, int q, int tid, int nth, int* cnt) {
+  if (tid == 0) *cnt = 0;
+  __syncthreads();
+  int any = 0;
+  for (int idx = tid; idx < q * q; idx += nth) {
+    const int i = idx / q, j = idx % q;
+    if (i < j && rotates(A[idx], A[i * q + i], A[j * q + j])) any = 1;
+  }
+  if (any) atomicOr(cnt, 1);
+  __syncthreads();
+  return *cnt == 0;
+}
+
 __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   const Layout L = Layout::make(f.p);
   const uint64_t* st = f.state;
@@ -218,6 +240,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
 
   __shared__ int s_flag;
   __shared__ int s_rot;
+  __shared__ int s_conv;  // converged(): its own word, so that no wave reads s_rot after a reset
   const int m = q + (q & 1);  // players (a dummy when q is odd)
   const int npairs = m / 2;
   // c[npairs], s[npairs], t[npairs], apq[npairs], the round's pairs, A, V
@@ -374,7 +397,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
         }
         __syncthreads();
       }
-      if (s_rot == 0) break;
+      if (s_rot == 0 || converged(A, q, tid, nth, &s_conv)) break;
       __syncthreads();
     }
   } else {
@@ -398,7 +421,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
       jacobi_vectors(V, q, npairs, R, tid, nth);
       __syncthreads();
     }
-    if (s_rot == 0) break;
+    if (s_rot == 0 || converged(A, q, tid, nth, &s_conv)) break;
     __syncthreads();
   }
   }
