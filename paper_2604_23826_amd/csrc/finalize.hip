@@ -252,9 +252,7 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
 
   if (f.phase == kPost) {
     if (f.jc[1]) return;  // non-finite input: the pre phase wrote NaN
-    goto sort_and_sign;
-  }
-  {
+  } else {
   // ---- means and covariance ----
   const double dn = (double)(n - f.ddof);
   for (int a = tid; a < q; a += nth) {
@@ -425,9 +423,8 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
     __syncthreads();
   }
   }
-  }
+  }  // phase kAll / kPre
 
-sort_and_sign:
   // ---- sort descending (ties: lower index first), sign rule, percentages ----
   for (int k = tid; k < q; k += nth) {
     const double lk = A[(int64_t)k * q + k];
