@@ -689,7 +689,7 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   const size_t out_words = (size_t)q * 4 + 3 * (size_t)q * q;
   rc = ensure_dev(h, (void**)&h->fin_out, &h->fin_out_cap, out_words * 8);
   const size_t jtab_words = 5 * (size_t)((q + 1) / 2);
-  if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, (2 * (size_t)q * q + jtab_words + 1) * 8);
+  if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, (2 * (size_t)q * q + jtab_words + 2) * 8);
   if (!rc) rc = ensure_dev(h, (void**)&h->sel_dev, &h->sel_cap, (size_t)q * 4);
   if (rc) return rc;
   e = hipMemcpyAsync(h->sel_dev, sel.data(), (size_t)q * 4, hipMemcpyHostToDevice, h->stream);

@@ -409,7 +409,7 @@ struct FinalizeLaunch {
   double* out;      // mean q, cov q*q, corr q*q, eigval q, eigvec q*q, var q, cum q
   double* scratch;  // 2 q*q (Jacobi A and V)
   double* jtab;     // q > 60: 5 * ceil(q / 2) (rotation tables of a round)
-  unsigned* jc;     // q > 60: 2 words (rotation count, non-finite flag)
+  unsigned* jc;     // q > 60: 3 words (rotations, non-finite flag, pairs still to rotate)
 };
 // Enqueues the finalize kernels on s.  Matrices above 60 x 60 run one kernel
 // pair per Jacobi round and wait on s after every sweep.

@@ -44,7 +44,8 @@ struct Args {
   double* scratch;
   int lds_mat;  // A and V in dynamic LDS after the rotation tables
   int phase;     // kAll, or kPre / kPost around the multi-kernel Jacobi
-  unsigned* jc;  // kPre / kPost: [0] rotations of a sweep, [1] non-finite input
+  unsigned* jc;  // kPre / kPost: [0] rotations of a sweep, [1] non-finite input,
+                 // [2] pairs that would still rotate after the sweep
 };
 
 enum { kAll = 0, kPre = 1, kPost = 2 };
@@ -484,6 +485,18 @@ __global__ __launch_bounds__(kThreads) void k_jrot(const double* __restrict__ A,
   if (cnt) atomicAdd(&jc[0], cnt);
 }
 
+// End of a sweep: count (into jc[2]) the pairs that would still rotate; none
+// means the next sweep would change nothing.
+__global__ __launch_bounds__(kJThreads) void k_jcheck(const double* __restrict__ A, int q, unsigned* jc) {
+  const int64_t n = (int64_t)q * q;
+  unsigned any = 0;
+  for (int64_t idx = (int64_t)blockIdx.x * kJThreads + threadIdx.x; idx < n; idx += (int64_t)gridDim.x * kJThreads) {
+    const int i = (int)(idx / q), j = (int)(idx % q);
+    if (i < j && rotates(A[idx], A[(int64_t)i * q + i], A[(int64_t)j * q + j])) any = 1;
+  }
+  if (any) atomicOr(&jc[2], 1u);
+}
+
 __global__ __launch_bounds__(kJThreads) void k_japply(double* A, double* V, int q, int m, const double* tab) {
   const int npairs = m / 2;
   extern __shared__ double s_tab[];  // the round's tables, copied once
@@ -583,10 +596,17 @@ hipError_t launch_finalize(const FinalizeLaunch& F, hipStream_t s) {
       hipLaunchKernelGGL(k_japply, dim3(nwg), dim3(kJThreads), tab_shm, s, A, V, F.q, m, F.jtab);
       e = hipGetLastError();
     }
-    unsigned rot = 0;
-    if (e == hipSuccess) e = hipMemcpyAsync(&rot, F.jc, sizeof(unsigned), hipMemcpyDeviceToHost, s);
+    // stop when this sweep rotated nothing, or when nothing would rotate in
+    // the next one (same result, one sweep earlier)
+    if (e == hipSuccess) e = hipMemsetAsync(F.jc + 2, 0, sizeof(unsigned), s);
+    if (e == hipSuccess) {
+      hipLaunchKernelGGL(k_jcheck, dim3(nwg), dim3(kJThreads), 0, s, A, F.q, F.jc);
+      e = hipGetLastError();
+    }
+    unsigned w[3] = {0, 0, 0};
+    if (e == hipSuccess) e = hipMemcpyAsync(w, F.jc, sizeof w, hipMemcpyDeviceToHost, s);
     if (e == hipSuccess) e = hipStreamSynchronize(s);
-    if (e != hipSuccess || rot == 0) break;
+    if (e != hipSuccess || w[0] == 0 || w[2] == 0) break;
   }
   if (e != hipSuccess) return e;
   a.phase = kPost;
