@@ -406,7 +406,7 @@ def run_groups(args, L, torch, datagen):
     out["steps"] = 1
     out["warmup"] = min(args.warmup, 1)
     out["roofline"] = add_measured_read(
-        hbm_roofline("k_seg_aos64 + k_seg_merge (graph)", total * 256, kms, n1 - n0,
+        hbm_roofline("k_seg_aos64 + k_seg_part + k_seg_fold (graph)", total * 256, kms, n1 - n0,
                      total * 256 / max(n1 - n0, 1)), L, [buf.data_ptr()], [wave_rows * 256], stream)
     out["finalize_groups_ms"] = round(1e3 * (tf1 - tf0), 1)
     out["identifier_closed_forms"] = f"{G - bad}/{G} groups exact"
