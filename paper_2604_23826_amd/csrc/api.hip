@@ -113,10 +113,8 @@ hipError_t clear_status(stats_ctx* h) {
   return hipMemcpyAsync(h->status_dev, &init, sizeof init, hipMemcpyHostToDevice, h->stream);
 }
 
-int check_status(stats_ctx* h) {
-  DevStatus s;
-  hipError_t e = hipMemcpy(&s, h->status_dev, sizeof s, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpy(status)");
+// The error recorded in a status word read back from the device, if any.
+static int status_error(const DevStatus& s) {
   if (s.bits & ST_PARSE) {
     char buf[128];
     snprintf(buf, sizeof buf, "malformed text field at byte offset %llu",
@@ -128,6 +126,13 @@ int check_status(stats_ctx* h) {
                 "an integer column left the exact range (non-integer value, |x - shift|^2 sum "
                 ">= 2^53 in a block, or |value| >= 2^40)");
   return STATS_OK;
+}
+
+int check_status(stats_ctx* h) {
+  DevStatus s;
+  hipError_t e = hipMemcpy(&s, h->status_dev, sizeof s, hipMemcpyDeviceToHost);
+  if (e != hipSuccess) return hip_fail(h, e, "hipMemcpy(status)");
+  return status_error(s);
 }
 
 int sync_handle(stats_ctx* h) {
@@ -679,12 +684,9 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   int rc = selection(h, o, &sel);
   if (rc) return rc;
   DeviceGuard g(h->device);
-  rc = sync_handle(h);
-  if (rc) return rc;
-  int64_t n = 0;
-  hipError_t e = hipMemcpy(&n, h->state[h->cur], 8, hipMemcpyDeviceToHost);
-  if (e != hipSuccess) return hip_fail(h, e, "reading n");
-  if (n <= o->ddof) return fail(STATS_E_STATE, "N <= ddof: covariance undefined");
+  // everything is enqueued behind the pending accumulate work and read back
+  // with one synchronization; the status word and N are checked afterwards
+  // (the kernel computes nothing when N <= ddof)
   const int q = (int)sel.size();
   const size_t out_words = (size_t)q * 4 + 3 * (size_t)q * q;
   rc = ensure_dev(h, (void**)&h->fin_out, &h->fin_out_cap, out_words * 8);
@@ -692,7 +694,7 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   if (!rc) rc = ensure_dev(h, (void**)&h->fin_scratch, &h->fin_scratch_cap, (2 * (size_t)q * q + jtab_words + 2) * 8);
   if (!rc) rc = ensure_dev(h, (void**)&h->sel_dev, &h->sel_cap, (size_t)q * 4);
   if (rc) return rc;
-  e = hipMemcpyAsync(h->sel_dev, sel.data(), (size_t)q * 4, hipMemcpyHostToDevice, h->stream);
+  hipError_t e = hipMemcpyAsync(h->sel_dev, sel.data(), (size_t)q * 4, hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "uploading selection");
   FinalizeLaunch F;
   F.state = h->state[h->cur];
@@ -715,10 +717,18 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   }
   if (e != hipSuccess) return hip_fail(h, e, "finalize");
   std::vector<double> out(out_words);
+  int64_t n = 0;
+  DevStatus st;
   e = hipMemcpyAsync(out.data(), h->fin_out, out_words * 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&n, h->state[h->cur], 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipMemcpyAsync(&st, h->status_dev, sizeof st, hipMemcpyDeviceToHost, h->stream);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e == hipSuccess && h->copy_stream) e = hipStreamSynchronize(h->copy_stream);
   if (e != hipSuccess) return hip_fail(h, e, "finalize");
   collect_timings(h);
+  rc = status_error(st);
+  if (rc) return rc;
+  if (n <= o->ddof) return fail(STATS_E_STATE, "N <= ddof: covariance undefined");
   const size_t qq = (size_t)q * q;
   const double* po = out.data();
   if (p_out) *p_out = q;

@@ -44,7 +44,8 @@ struct Args {
   double* scratch;
   int lds_mat;  // A and V in dynamic LDS after the rotation tables
   int phase;     // kAll, or kPre / kPost around the multi-kernel Jacobi
-  unsigned* jc;  // kPre / kPost: [0] rotations of a sweep, [1] non-finite input,
+  unsigned* jc;  // kPre / kPost: [0] rotations of a sweep, [1] no decomposition (non-finite
+                 // input, or n <= ddof),
                  // [2] pairs that would still rotate after the sweep
 };
 
@@ -252,7 +253,15 @@ __global__ __launch_bounds__(kThreads) void k_finalize(Args f) {
   double* V = A + (int64_t)q * q;
 
   if (f.phase == kPost) {
-    if (f.jc[1]) return;  // non-finite input: the pre phase wrote NaN
+    if (f.jc[1]) return;  // no decomposition: see the pre phase
+  } else if (n <= f.ddof) {
+    // covariance undefined (the host reports it); nothing is computed, and
+    // the exact divisions by n and n - ddof are never reached
+    if (f.phase == kPre && tid == 0) {
+      f.jc[0] = 0;
+      f.jc[1] = 1;
+    }
+    return;
   } else {
   // ---- means and covariance ----
   const double dn = (double)(n - f.ddof);
@@ -475,7 +484,7 @@ __global__ __launch_bounds__(kThreads) void k_jrot(const double* __restrict__ A,
     int a, b;
     rr_pair(k, r, m, a, b);
     double c = 1.0, s = 0.0, t = 0.0, apq = 0.0;
-    if (b < q && jacobi_rotation(A, q, a, b, c, s, t, apq)) ++cnt;
+    if (!jc[1] && b < q && jacobi_rotation(A, q, a, b, c, s, t, apq)) ++cnt;
     R.c[k] = c;
     R.s[k] = s;
     R.t[k] = t;

@@ -293,3 +293,43 @@ def test_read_probe_times_reads_and_checks_arguments():
         with pytest.raises(L.StatsError) as e:
             L.stats_read_probe(bufs, sizes, current_stream())
         assert e.value.code == L.STATS_E_ARG
+
+
+def test_finalize_errors_after_one_readback():
+    """stats_finalize reads N and the status word back with its outputs: N <=
+    ddof is STATS_E_STATE (small and multi-kernel eigensolver sizes), an
+    inexact integer column is STATS_E_INEXACT, and a valid call on the same
+    handle afterwards still returns the oracle's result."""
+    L = lib()
+    for p in (10, 65):
+        x = np.zeros((1, p))
+        x[0] = np.arange(p)
+        h = L.stats_open(aos_config(p=p, int_cols=[True] * p, stream=current_stream()))
+        try:
+            L.stats_accumulate(h, [to_dev(x)], 1)
+            with pytest.raises(L.StatsError) as e:
+                L.stats_finalize(h, p)
+            assert e.value.code == L.STATS_E_STATE
+            fin0 = L.stats_finalize(h, p, ddof=0)  # n = 1, ddof = 0: zero covariance
+            assert np.all(fin0["cov"] == 0.0)
+        finally:
+            L.stats_close(h)
+    y = datagen.table1_aos(9, 5000)
+    y[77, 3] += 0.5  # D declared integer but holds a fraction
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(y)], 5000)
+        with pytest.raises(L.StatsError) as e:
+            L.stats_finalize(h, 10)
+        assert e.value.code == L.STATS_E_INEXACT
+    finally:
+        L.stats_close(h)
+    z = datagen.table1_aos(9, 5000)
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(z)], 5000)
+        fin = L.stats_finalize(h, 10)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(z), TABLE1_INT)
+    check_final_against_oracle(fin, oracle.finalize(st, mask=range(1, 10)), [TABLE1_INT[c] for c in range(1, 10)])
