@@ -218,21 +218,29 @@ def run_share(args, L, torch, datagen):
 
 def run_c1(args, L, torch, datagen):
     N = args.rows if args.rows_given else 1_000_000
+    P = args.p
     dev = torch.device("cuda:0")
     stream = torch.cuda.current_stream().cuda_stream
-    x = torch.empty((N, 10), dtype=torch.float64, device=dev)
-    datagen.dev_table1_aos(1, N, x.data_ptr(), stream=stream)
+    if P == 10:
+        x = torch.empty((N, 10), dtype=torch.float64, device=dev)
+        datagen.dev_table1_aos(1, N, x.data_ptr(), stream=stream)
+        int_cols = [True] * 8 + [False, True]
+    else:
+        # 16 integer-valued FP64 columns, U{0..999}, 128-byte rows
+        g = torch.Generator(device=dev)
+        g.manual_seed(16)
+        x = torch.randint(0, 1000, (N, P), generator=g, dtype=torch.float64, device=dev)
+        int_cols = [True] * P
     torch.cuda.synchronize()
-    int_cols = [True] * 8 + [False, True]
     cols = [(L.STATS_F64, 0, 8 * c, (L.STATS_COL_INTEGER if int_cols[c] else 0) |
-             (L.STATS_COL_IDENTIFIER if c == 0 else 0)) for c in range(10)]
-    h = L.stats_open(L.make_config(cols, [80], stream=stream, timing=True))
-    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev) if N * 80 < (1 << 29) else None
+             (L.STATS_COL_IDENTIFIER if (c == 0 and P == 10) else 0)) for c in range(P)]
+    h = L.stats_open(L.make_config(cols, [8 * P], stream=stream, timing=True))
+    flush = torch.empty(1 << 28, dtype=torch.float32, device=dev) if N * 8 * P < (1 << 29) else None
 
     def step():
         L.stats_reset(h)
         L.stats_accumulate(h, [x], N)
-        return L.stats_finalize(h, 10)
+        return L.stats_finalize(h, P)
 
     for _ in range(args.warmup):
         step()
@@ -248,17 +256,20 @@ def run_c1(args, L, torch, datagen):
         torch.cuda.synchronize()
         times.append(time.perf_counter() - t0)
     n1, ms1 = L.stats_kernel_time(h, L.STATS_K_ACCUM)
-    raw = L.stats_raw(h, 10)
-    assert raw["s_int"][0] == N * (N + 1) // 2
+    raw = L.stats_raw(h, P)
+    if P == 10:
+        assert raw["s_int"][0] == N * (N + 1) // 2
     L.stats_close(h)
     el = sum(times)
-    roof = hbm_roofline("accum_small_p (p=10, FP64 rows)", N * args.steps * 80, ms1 - ms0, n1 - n0,
-                        N * 80 * args.steps / max(n1 - n0, 1))
+    B = 8 * P
+    roof = hbm_roofline(f"accum_small_p (p={P}, FP64 rows)", N * args.steps * B, ms1 - ms0, n1 - n0,
+                        N * B * args.steps / max(n1 - n0, 1))
+    name = f"table1_fp64_aos_{N}_rows" if P == 10 else f"uint_fp64_aos_{N}_rows_p{P}"
     out = base_json(args, N * args.steps / el, "rows/s", 1e3 * el / args.steps, "f64",
-                    {"workload": f"table1_fp64_aos_{N}_rows", "rows": N, "p": 10, "bytes_per_row": 80,
+                    {"workload": name, "rows": N, "p": P, "bytes_per_row": B,
                      "cache_flushed_between_steps": flush is not None,
                      "step": "reset + accumulate + finalize (cov, corr, PCA)"})
-    out["roofline"] = add_measured_read(roof, L, [x.data_ptr()], [N * 80], stream)
+    out["roofline"] = add_measured_read(roof, L, [x.data_ptr()], [N * B], stream)
     out["eigval_top3"] = [float(v) for v in fin["eigval"][:3]]
     return out
 
@@ -492,6 +503,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="share", choices=["share", "c1", "wide", "groups", "text"])
     ap.add_argument("--rows", type=int, default=None)
+    ap.add_argument("--p", type=int, default=10, choices=[10, 16], help="c1: columns (16 = 128-byte rows)")
     ap.add_argument("--chunk-rows", type=int, default=1 << 28)
     ap.add_argument("--wave-rows", type=int, default=600_000_000)
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 26)
