@@ -565,8 +565,9 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
       }
     }
     __syncthreads();
-    // round 0 parses only; line 0 is the workgroup's first line, whose row
-    // (copied by thread 0 before the barrier) is the block shift
+    // the first pass (lines 0..255) parses only; line 0 is the workgroup's
+    // first line, whose row (copied by thread 0 before the barrier) is the
+    // block shift
     int end0 = -1, bad0 = INT32_MAX;
     uint64_t* row0 = s_row[threadIdx.x];
     if ((int)threadIdx.x < total) end0 = parse_line(a, C, (int)s_ls[threadIdx.x], row0, &bad0);
