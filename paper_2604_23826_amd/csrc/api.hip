@@ -11,6 +11,7 @@
 
 #include "common.hpp"
 #include "runtime.hpp"
+#include "wide.hpp"
 
 using namespace st;
 
@@ -337,11 +338,94 @@ static int64_t auto_block_rows(int64_t nrows) {
   return std::max<int64_t>(4096, std::min<int64_t>(R, (int64_t)1 << 17));
 }
 
+// FP64 row-major records of 128 bytes holding 11 <= p <= 16 columns at byte
+// offsets 8c, 16-byte aligned: the FP64 matrix-core kernel (one 16x16x4
+// product per 4 rows) instead of per-lane accumulators, whose 136 products
+// would leave one wave per SIMD.
+static bool aos128_layout(const stats_ctx* h, const void* const* planes) {
+  if (h->p < 11 || h->p > 16) return false;
+  const int pl = h->cols[0].plane;
+  if (h->row_stride[pl] != 128 || ((uintptr_t)planes[pl] & 15u) != 0) return false;
+  for (int c = 0; c < h->p; ++c) {
+    const stats_column& col = h->cols[c];
+    if (col.plane != pl || col.dtype != STATS_F64 || col.byte_offset != 8 * c) return false;
+  }
+  return true;
+}
+
+static int accumulate_aos128(stats_ctx* h, const void* const* planes, int64_t nrows, int64_t R) {
+  const int p = h->p;
+  const int pl = h->cols[0].plane;
+  // slot table and queue word in aux3 (used by the wide path only, p > 16)
+  const size_t slot_bytes = (sizeof(wide::SlotInfo) * (size_t)p + 255) / 256 * 256;
+  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, slot_bytes + 256);
+  if (rc) return rc;
+  wide::SlotInfo* slots_dev = (wide::SlotInfo*)h->aux3_dev;
+  unsigned long long* counter = (unsigned long long*)((char*)h->aux3_dev + slot_bytes);
+  int ncu = 256;
+  (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
+  const int64_t W = rec_words(p);
+  const int64_t max_rows = ((int64_t)1 << 28) / R * R;
+  std::vector<wide::SlotInfo> slots(p);
+  int64_t done = 0;
+  while (done < nrows) {
+    const int64_t rows = std::min(nrows - done, max_rows);
+    const int64_t nblocks = (rows + R - 1) / R;
+    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    if (rc) return rc;
+    for (int c = 0; c < p; ++c) {
+      const stats_column& col = h->cols[c];
+      wide::SlotInfo& sl = slots[c];
+      sl.stride = 128;
+      sl.base = (const char*)planes[pl] + 8 * c + done * 128;
+      sl.kind = col.dtype;
+      sl.chk = (col.flags & STATS_COL_INTEGER) ? 1 : 0;
+      sl.isint = h->intf[c];
+      sl.pad[0] = sl.pad[1] = 0;
+    }
+    // ordered after the previous launch, which has read the table
+    hipError_t e = hipMemcpyAsync(slots_dev, slots.data(), sizeof(wide::SlotInfo) * (size_t)p,
+                                  hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
+    wide::Args a;
+    memset(&a, 0, sizeof a);
+    a.slots = slots_dev;
+    a.p = p;
+    a.nblocks = nblocks;
+    a.nrows = rows;
+    a.R = R;
+    a.rec = h->rec;
+    a.status = h->status_dev;
+    wide::SegArgs g{nullptr, nullptr, counter, R, rows};
+    {
+      Timer t;
+      t.begin(h, STATS_K_ACCUM);
+      launch_seg_aos64(a, g, (int)std::min<int64_t>(nblocks, (int64_t)ncu * 8), h->stream, 128);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "accumulate kernel launch");
+    {
+      Timer t;
+      t.begin(h, STATS_K_MERGE);
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1],
+                           h->status_dev, h->stream);
+      t.end();
+    }
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "merge kernel launch");
+    h->cur ^= 1;
+    done += rows;
+  }
+  return STATS_OK;
+}
+
 // Reduce nrows device-resident rows (plane bases already offset to the first
 // row) into the handle state.  Small p only (p <= 16).
 int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nrows) {
   const int p = h->p;
   const int64_t R = h->block_rows ? h->block_rows : auto_block_rows(nrows);
+  if (aos128_layout(h, planes)) return accumulate_aos128(h, planes, nrows, R);
   AccumLaunch a;
   memset(&a, 0, sizeof a);
   a.p = p;

@@ -1,5 +1,7 @@
-// Batched groups on FP64 row-major records: all p <= 32 columns FP64 at byte
-// offsets 8c of 256-byte rows (the batched workload's layout).
+// FP64 row-major records on the FP64 matrix cores: all p columns FP64 at byte
+// offsets 8c of RS-byte rows, RS = 256 (p <= 32: the batched workload's
+// layout) or RS = 128 (p <= 16).  Items come from a tile table (groups) or
+// are uniform blocks of rows (one table).
 //
 // Same contract as the persistent segmented kernel of wide.hip (items = row
 // tiles of groups from an atomic queue, one block record per row tile, merged
@@ -27,11 +29,8 @@ namespace aos64 {
 typedef double d4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int kRS = 256;      // bytes per row
 constexpr int kSR = 64;       // rows per stage
-constexpr int kSB = kSR * kRS;  // stage bytes
 constexpr int kNS = 3;        // stages in LDS
-constexpr int kLPW = kSB / 1024 / 4;  // 1 KiB DMA pieces per wave per stage (4)
 
 // Cache-policy operand of the DMA loads: non-temporal (each row is read once).
 constexpr int kNonTemporal = 2;
@@ -43,8 +42,20 @@ struct VmWait {
 };
 
 // The four 4-row steps of a wave's 16 rows: values of columns c and c + 16 of
-// rows a/256 + 4s, read in one asm block (with its own completion wait) so
-// that the compiler does not make them wait for the DMA stages in flight.
+// rows a/256 + 4s (256-byte rows), or of column c of rows a/128 + 4s (128-byte
+// rows), read in one asm block (with its own completion wait) so that the
+// compiler does not make them wait for the DMA stages in flight.
+__device__ inline void lds_steps128(uint32_t a, double (&x0)[4]) {
+  asm volatile(
+      "ds_read_b64 %0, %4\n\t"
+      "ds_read_b64 %1, %4 offset:512\n\t"
+      "ds_read_b64 %2, %4 offset:1024\n\t"
+      "ds_read_b64 %3, %4 offset:1536\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x0[0]), "=&v"(x0[1]), "=&v"(x0[2]), "=&v"(x0[3])
+      : "v"(a));
+}
+
 __device__ inline void lds_steps(uint32_t a, double (&x0)[4], double (&x1)[4]) {
   asm volatile(
       "ds_read_b64 %0, %8\n\t"
@@ -63,9 +74,10 @@ __device__ inline void lds_steps(uint32_t a, double (&x0)[4], double (&x1)[4]) {
 
 __device__ inline uint32_t not_integer(double v) { return v != __builtin_rint(v) ? 1u : 0u; }
 
+template <int RS>
 struct Smem {
   union {
-    unsigned char st[kNS][kSB];  // stage ring
+    unsigned char st[kNS][kSR * RS];  // stage ring
     struct {
       double acc[4][3][4][64];     // per wave: tiles x registers x lanes
       double s[4][64][2];          // per wave and lane: sums of columns c, c + 16
@@ -76,8 +88,14 @@ struct Smem {
   int64_t item;
 };
 
+template <int RS>
 __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegArgs g) {
-  __shared__ __attribute__((aligned(16))) Smem sm;
+  constexpr int kRS = RS;
+  constexpr int kSB = kSR * RS;          // stage bytes
+  constexpr int kLPW = kSB / 1024 / 4;   // 1 KiB DMA pieces per wave per stage
+  constexpr bool kTwo = RS == 256;       // a second half of 16 columns
+  constexpr int kTiles = kTwo ? 3 : 1;   // upper 16 x 16 tiles
+  __shared__ __attribute__((aligned(16))) Smem<RS> sm;
   const int p = a.p;
   const int tid = threadIdx.x, lane = tid & 63, q16 = lane & 15, kq = lane >> 4;
   const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);
@@ -92,7 +110,7 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
     sm.isint = isint;
   }
   const int c0 = q16, c1 = 16 + q16;
-  const int64_t nitems = *g.nrowtiles;
+  const int64_t nitems = g.tile_rows ? (g.total_rows + g.tile_rows - 1) / g.tile_rows : *g.nrowtiles;
   const uint32_t lds0 = (uint32_t)(uintptr_t)(__attribute__((address_space(3))) unsigned char*)&sm.u.st[0][0];
   for (;;) {
     __syncthreads();  // previous item's LDS use is over
@@ -100,11 +118,18 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
     __syncthreads();
     const int64_t item = sm.item;
     if (item >= nitems) break;
-    const wide::SegTile tile = g.rowtiles[item];
-    const int64_t r0 = tile.r0, r1 = tile.r1;
+    int64_t r0, r1;
+    if (g.tile_rows) {
+      r0 = item * g.tile_rows;
+      r1 = min(r0 + g.tile_rows, g.total_rows);
+    } else {
+      const wide::SegTile tile = g.rowtiles[item];
+      r0 = tile.r0;
+      r1 = tile.r1;
+    }
     if (tid < p) sm.K[tid] = *(const double*)(base + r0 * kRS + 8 * tid);
     __syncthreads();
-    const bool v0ok = c0 < p, v1ok = c1 < p;
+    const bool v0ok = c0 < p, v1ok = kTwo && c1 < p;
     const double K0 = v0ok ? sm.K[c0] : 0.0, K1 = v1ok ? sm.K[c1] : 0.0;
     const uint32_t chk0 = (sm.chk >> c0) & 1u, chk1 = v1ok ? (sm.chk >> c1) & 1u : 0u;
     d4 acc00 = (d4){0.0, 0.0, 0.0, 0.0}, acc01 = acc00, acc11 = acc00;
@@ -115,10 +140,12 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
       if (chk0) bad |= not_integer(x0);
       if (chk1) bad |= not_integer(x1);
       S0 += v0;
-      S1 += v1;
       acc00 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, v0, acc00, 0, 0, 0);
-      acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, v1, acc01, 0, 0, 0);
-      acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, v1, acc11, 0, 0, 0);
+      if constexpr (kTwo) {
+        S1 += v1;
+        acc01 = __builtin_amdgcn_mfma_f64_16x16x4f64(v0, v1, acc01, 0, 0, 0);
+        acc11 = __builtin_amdgcn_mfma_f64_16x16x4f64(v1, v1, acc11, 0, 0, 0);
+      }
     };
 
     const int64_t nst = (r1 - r0) / kSR;  // whole stages
@@ -141,8 +168,10 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
       if (t + kNS - 2 < nst) __builtin_amdgcn_s_waitcnt(VmWait<(kNS - 2) * kLPW>::imm);
       else __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
       if (t + kNS - 1 < nst) issue(t + kNS - 1);
-      double x0[4], x1[4];
-      lds_steps(lds0 + (uint32_t)(t % kNS) * kSB + (uint32_t)(16 * wave + kq) * kRS + 8 * c0, x0, x1);
+      double x0[4], x1[4] = {0.0, 0.0, 0.0, 0.0};
+      const uint32_t la = lds0 + (uint32_t)(t % kNS) * kSB + (uint32_t)(16 * wave + kq) * kRS + 8 * c0;
+      if constexpr (kTwo) lds_steps(la, x0, x1);
+      else lds_steps128(la, x0);
 #pragma unroll
       for (int s = 0; s < 4; ++s) step(x0[s], x1[s]);
     }
@@ -173,8 +202,8 @@ __global__ __launch_bounds__(kThreads) void k_seg_aos64(wide::Args a, wide::SegA
     sm.u.red.s[wave][lane][1] = S1;
     __syncthreads();
     uint64_t* out = a.rec + item * rec_words(p);
-    // 3 tiles x 4 registers x 64 lanes = 768 entries, three per thread
-    for (int e = tid; e < 3 * 4 * 64; e += kThreads) {
+    // tiles x 4 registers x 64 lanes, in fixed order
+    for (int e = tid; e < kTiles * 4 * 64; e += kThreads) {
       const int tile_ = e >> 8, r = (e >> 6) & 3, l = e & 63;
       double v = sm.u.red.acc[0][tile_][r][l];
 #pragma unroll
@@ -209,9 +238,12 @@ __global__ void k_zero_queue(unsigned long long* c) { *c = 0ull; }
 
 }  // namespace aos64
 
-void launch_seg_aos64(const wide::Args& a, const wide::SegArgs& g, int nwg, hipStream_t s) {
+void launch_seg_aos64(const wide::Args& a, const wide::SegArgs& g, int nwg, hipStream_t s, int row_bytes) {
   hipLaunchKernelGGL(aos64::k_zero_queue, dim3(1), dim3(1), 0, s, g.counter);
-  hipLaunchKernelGGL(aos64::k_seg_aos64, dim3(nwg), dim3(aos64::kThreads), 0, s, a, g);
+  if (row_bytes == 128)
+    hipLaunchKernelGGL(aos64::k_seg_aos64<128>, dim3(nwg), dim3(aos64::kThreads), 0, s, a, g);
+  else
+    hipLaunchKernelGGL(aos64::k_seg_aos64<256>, dim3(nwg), dim3(aos64::kThreads), 0, s, a, g);
 }
 
 }  // namespace st

@@ -44,6 +44,8 @@ struct SegArgs {
   const SegTile* rowtiles;            // row tiles, sorted by group (device)
   const int64_t* nrowtiles;           // number of row tiles (device word)
   unsigned long long* counter;        // work queue head (device word)
+  int64_t tile_rows = 0;              // > 0: no table; item k is rows [k tile_rows,
+  int64_t total_rows = 0;             //   min((k + 1) tile_rows, total_rows))
 };
 
 // FP32 matrix on BF16 matrix cores (wide_syrk.hip): F vector columns at
@@ -83,7 +85,7 @@ void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s);
 // Persistent segmented launch (zeroes the queue first): nwg workgroups.
 void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s);
 // The same for FP64 records of 256 bytes, column c at byte 8c, p <= 32.
-void launch_seg_aos64(const wide::Args& a, const wide::SegArgs& g, int nwg, hipStream_t s);
+void launch_seg_aos64(const wide::Args& a, const wide::SegArgs& g, int nwg, hipStream_t s, int row_bytes = 256);
 
 // st = super-group width (32 or 64); mode = MODE_FP64 or MODE_SPLIT.
 void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s);

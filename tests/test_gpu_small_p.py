@@ -333,3 +333,32 @@ def test_finalize_errors_after_one_readback():
         L.stats_close(h)
     st = oracle.sufficient_stats(oracle.columns_of(z), TABLE1_INT)
     check_final_against_oracle(fin, oracle.finalize(st, mask=range(1, 10)), [TABLE1_INT[c] for c in range(1, 10)])
+
+
+@pytest.mark.parametrize("p", [11, 16])
+@pytest.mark.parametrize("n,block_rows", [(1, 0), (65, 0), (70_001, 4096), (200_003, 0)])
+def test_fp64_rows_of_128_bytes_on_matrix_cores(p, n, block_rows):
+    """FP64 records of 128 bytes with 11..16 columns go to the FP64
+    matrix-core kernel (64-row LDS stages, one 16x16x4 product per 4 rows):
+    integer columns exact, the rest within 1e-12; ragged last blocks and
+    stages read directly."""
+    L = lib()
+    rng = np.random.default_rng(p * 1000 + n)
+    x = np.zeros((n, 16))
+    ni = p - 4
+    x[:, :ni] = rng.integers(-1000, 1000, size=(n, ni))
+    x[:, ni:p] = rng.standard_normal((n, 4)) * 10.0 + 3.0
+    x[:, p:] = np.nan  # unused bytes of the row
+    int_cols = [True] * ni + [False] * 4
+    cols = [(L.STATS_F64, 0, 8 * c, L.STATS_COL_INTEGER if int_cols[c] else 0) for c in range(p)]
+    h = L.stats_open(L.make_config(cols, [128], stream=current_stream(), block_rows=block_rows))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], n)
+        raw = L.stats_raw(h, p)
+        fin = L.stats_finalize(h, p) if n > 1 else None
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats([x[:, c] for c in range(p)], int_cols)
+    check_raw_against_oracle(raw, st, int_cols)
+    if fin is not None:
+        check_final_against_oracle(fin, oracle.finalize(st), int_cols)
