@@ -338,14 +338,14 @@ static int64_t auto_block_rows(int64_t nrows) {
   return std::max<int64_t>(4096, std::min<int64_t>(R, (int64_t)1 << 17));
 }
 
-// FP64 row-major records of 128 bytes holding 11 <= p <= 16 columns at byte
-// offsets 8c, 16-byte aligned: the FP64 matrix-core kernel (one 16x16x4
-// product per 4 rows) instead of per-lane accumulators, whose 136 products
-// would leave one wave per SIMD.
-static bool aos128_layout(const stats_ctx* h, const void* const* planes) {
-  if (h->p < 11 || h->p > 16) return false;
+// FP64 row-major records of RS bytes with every column at byte offset 8c,
+// 16-byte aligned: the FP64 matrix-core kernel k_seg_aos64<RS> (one 16x16x4
+// product per 4 rows and 16 columns).  Used for RS = 128 with 11 <= p <= 16,
+// where per-lane accumulators (136 products) would leave one wave per SIMD,
+// and for RS = 256 with 17 <= p <= 32 in FP64 mode.
+static bool aos_rows_layout(const stats_ctx* h, const void* const* planes, int RS) {
   const int pl = h->cols[0].plane;
-  if (h->row_stride[pl] != 128 || ((uintptr_t)planes[pl] & 15u) != 0) return false;
+  if (h->row_stride[pl] != RS || ((uintptr_t)planes[pl] & 15u) != 0) return false;
   for (int c = 0; c < h->p; ++c) {
     const stats_column& col = h->cols[c];
     if (col.plane != pl || col.dtype != STATS_F64 || col.byte_offset != 8 * c) return false;
@@ -353,7 +353,7 @@ static bool aos128_layout(const stats_ctx* h, const void* const* planes) {
   return true;
 }
 
-static int accumulate_aos128(stats_ctx* h, const void* const* planes, int64_t nrows, int64_t R) {
+static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t nrows, int64_t R, int RS) {
   const int p = h->p;
   const int pl = h->cols[0].plane;
   // slot table and queue word in aux3 (used by the wide path only, p > 16)
@@ -376,8 +376,8 @@ static int accumulate_aos128(stats_ctx* h, const void* const* planes, int64_t nr
     for (int c = 0; c < p; ++c) {
       const stats_column& col = h->cols[c];
       wide::SlotInfo& sl = slots[c];
-      sl.stride = 128;
-      sl.base = (const char*)planes[pl] + 8 * c + done * 128;
+      sl.stride = RS;
+      sl.base = (const char*)planes[pl] + 8 * c + done * RS;
       sl.kind = col.dtype;
       sl.chk = (col.flags & STATS_COL_INTEGER) ? 1 : 0;
       sl.isint = h->intf[c];
@@ -400,7 +400,7 @@ static int accumulate_aos128(stats_ctx* h, const void* const* planes, int64_t nr
     {
       Timer t;
       t.begin(h, STATS_K_ACCUM);
-      launch_seg_aos64(a, g, (int)std::min<int64_t>(nblocks, (int64_t)ncu * 8), h->stream, 128);
+      launch_seg_aos64(a, g, (int)std::min<int64_t>(nblocks, (int64_t)ncu * 8), h->stream, RS);
       t.end();
     }
     e = hipGetLastError();
@@ -425,7 +425,7 @@ static int accumulate_aos128(stats_ctx* h, const void* const* planes, int64_t nr
 int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nrows) {
   const int p = h->p;
   const int64_t R = h->block_rows ? h->block_rows : auto_block_rows(nrows);
-  if (aos128_layout(h, planes)) return accumulate_aos128(h, planes, nrows, R);
+  if (p >= 11 && aos_rows_layout(h, planes, 128)) return accumulate_aos_rows(h, planes, nrows, R, 128);
   AccumLaunch a;
   memset(&a, 0, sizeof a);
   a.p = p;
@@ -478,6 +478,8 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
 
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
   if (h->p <= 16) return accumulate_device_small(h, planes, nrows);
+  if (h->p <= 32 && h->precision != STATS_PREC_SPLIT_BF16 && aos_rows_layout(h, planes, 256))
+    return accumulate_aos_rows(h, planes, nrows, h->block_rows ? h->block_rows : auto_block_rows(nrows), 256);
   return accumulate_device_wide(h, planes, nrows);
 }
 
