@@ -12,8 +12,17 @@ GPU-Accelerated Multivariate Statistics Platform"):
 * ``finalize`` -- means, covariance, correlation and the principal components
   derived from those statistics only (same section; section "Principal
   Component Analysis Results" and its Table 3 for the output form).
+* ``pca`` -- eigenvalues (descending), eigenvector rows, variance % and
+  cumulative % of a symmetric matrix (Table 3's columns); ``finalize`` uses
+  it.
+* ``integer_sums`` -- the exact (n, s, C) of integer-valued columns alone
+  (one __int128 pass), for checks at sizes where the full two-pass oracle is
+  too slow.
 * ``brute_force`` -- the same quantities with exact rational arithmetic
   (``fractions.Fraction``) for tiny inputs: the pin for everything above.
+
+Both passes can split their rows over host threads (``threads=``); the
+integer results do not depend on the split.
 * ``parse_csv`` -- strtod/strtoll parse of CSV text (section "Validation and
   Infrastructure Testing": the data starts as CSV text).
 
@@ -22,8 +31,12 @@ Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
 and never calls it.
 
 Parity pins (see tests/test_oracle_*.py): closed forms of the identifier
-column, exact brute force on tiny inputs, the worked example Table 2 ->
-Table 3, and the invariants of covariance / correlation / eigenpairs.
+column, exact brute force on tiny inputs (sums, cross products, means,
+co-moments, covariances), the worked example Table 2 -> Table 3 through
+``pca`` (eigenvalues, variance %, cumulative %, loadings), a diagonal
+covariance with closed-form PCA, matrices with known eigenpairs on both
+eigensolver branches, and the invariants of covariance / correlation /
+eigenpairs.
 """
 from __future__ import annotations
 
@@ -70,6 +83,8 @@ def _L() -> ctypes.CDLL:
         lib.oracle_pass1.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp]
         lib.oracle_pass2.restype = None
         lib.oracle_pass2.argtypes = [vp, i32, i64, i64, vp, vp]
+        lib.oracle_pass_int.restype = ctypes.c_int
+        lib.oracle_pass_int.argtypes = [vp, i32, i64, i64, vp, vp]
         lib.oracle_parse_csv.restype = i64
         lib.oracle_parse_csv.argtypes = [vp, i64, i32, vp, vp, i64]
         _lib = lib
@@ -152,11 +167,32 @@ def _pass2(cols, r0, r1, mu):
     return [Fraction(float(M2[2 * t])) + Fraction(float(M2[2 * t + 1])) for t in range(T)]
 
 
-def sufficient_stats_stream(chunks, is_int) -> OracleStats:
+def _over_ranges(fn, cols, m, threads, *extra):
+    """fn over the rows [0, m) of one batch, split into ``threads`` contiguous
+    row ranges run on host threads (the C calls release the interpreter
+    lock).  The partial results are exact integers and exact rationals
+    (``Fraction`` of each range's compensated (hi, lo) pair) and are added
+    exactly: the integer parts do not depend on the split, the compensated
+    parts only through each range's own compensated rounding (far below one
+    FP64 rounding of the result)."""
+    if threads <= 1 or m < 2 * threads:
+        return fn(cols, 0, m, *extra)
+    from concurrent.futures import ThreadPoolExecutor
+    cuts = [m * k // threads for k in range(threads + 1)]
+    with ThreadPoolExecutor(threads) as ex:
+        parts = list(ex.map(lambda k: fn(cols, cuts[k], cuts[k + 1], *extra), range(threads)))
+    if fn is _pass2:
+        return [sum(col, Fraction(0)) for col in zip(*parts)]
+    return tuple([sum(col, type(col[0])(0)) for col in zip(*field)] for field in zip(*parts))
+
+
+def sufficient_stats_stream(chunks, is_int, threads: int = 1) -> OracleStats:
     """Two passes over a re-iterable source of row chunks.
 
     ``chunks()`` returns an iterator of column lists (numpy 1-D arrays, one per
-    column, equal lengths); it is called twice (pass 1, pass 2)."""
+    column, equal lengths); it is called twice (pass 1, pass 2).  ``threads``
+    splits each batch into row ranges reduced on that many host threads
+    (identical integer results; see ``_over_ranges``)."""
     p = len(is_int)
     T = p * (p + 1) // 2
     n = 0
@@ -166,7 +202,7 @@ def sufficient_stats_stream(chunks, is_int) -> OracleStats:
     C_ex = [Fraction(0)] * T
     for cols in chunks():
         m = len(cols[0])
-        si, ci, sf, cf = _pass1(list(zip(cols, is_int)), 0, m)
+        si, ci, sf, cf = _over_ranges(_pass1, list(zip(cols, is_int)), m, threads)
         n += m
         s_int = [a + b for a, b in zip(s_int, si)]
         C_int = [a + b for a, b in zip(C_int, ci)]
@@ -185,7 +221,7 @@ def sufficient_stats_stream(chunks, is_int) -> OracleStats:
     if n:
         for cols in chunks():
             m = len(cols[0])
-            part = _pass2(list(zip(cols, is_int)), 0, m, mu)
+            part = _over_ranges(_pass2, list(zip(cols, is_int)), m, threads, mu)
             M2 = [a + b for a, b in zip(M2, part)]
         # Pass 2 centred on the rounded means mu; the identity
         # sum (x - a)(y - b) = M2 + n (mean_x - a)(mean_y - b) removes that.
@@ -208,10 +244,43 @@ def sufficient_stats_stream(chunks, is_int) -> OracleStats:
         s_exact=s_ex, C_exact=C_ex, M2=M2, mu=mu)
 
 
-def sufficient_stats(cols, is_int) -> OracleStats:
+def sufficient_stats(cols, is_int, threads: int = 1) -> OracleStats:
     """Statistics of one in-memory batch of columns."""
     cols = [np.ascontiguousarray(c) if np.asarray(c).ndim == 1 else c for c in cols]
-    return sufficient_stats_stream(lambda: iter([cols]), is_int)
+    return sufficient_stats_stream(lambda: iter([cols]), is_int, threads)
+
+
+def integer_sums(cols, threads: int = 1):
+    """Exact (n, s, C) of integer-valued columns only: s_i = sum x_i and
+    C_ij = sum x_i x_j (i <= j, packed upper triangle) as Python ints, from
+    one __int128 pass per row range (section "Data Representation and
+    Sufficient Statistics").  Raises ValueError on a non-integer value."""
+    cols = [np.ascontiguousarray(c) for c in cols]
+    p = len(cols)
+    T = p * (p + 1) // 2
+    m = len(cols[0]) if p else 0
+
+    def run(_cols, r0, r1):
+        arr, keep = _cols_struct([(c, True) for c in cols])
+        s = np.zeros(2 * p, dtype=np.uint64)
+        C = np.zeros(2 * T, dtype=np.uint64)
+        bad = _L().oracle_pass_int(arr, p, r0, r1, s.ctypes.data, C.ctypes.data)
+        del keep
+        if bad:
+            raise ValueError("integer column holds a non-integer value")
+        return ([_i128(s[2 * i], s[2 * i + 1]) for i in range(p)],
+                [_i128(C[2 * t], C[2 * t + 1]) for t in range(T)])
+
+    if threads <= 1 or m < 2 * threads:
+        s, C = run(cols, 0, m)
+    else:
+        from concurrent.futures import ThreadPoolExecutor
+        cuts = [m * k // threads for k in range(threads + 1)]
+        with ThreadPoolExecutor(threads) as ex:
+            parts = list(ex.map(lambda k: run(cols, cuts[k], cuts[k + 1]), range(threads)))
+        s = [sum(v) for v in zip(*(q[0] for q in parts))]
+        C = [sum(v) for v in zip(*(q[1] for q in parts))]
+    return m, s, C
 
 
 # ---- derived quantities -----------------------------------------------------
@@ -281,19 +350,27 @@ def finalize(st: OracleStats, mask=None, ddof: int = 1, pca_on: str = "corr"):
                 else:
                     corr[a, b] = float(mpmath.mpf(cov[a, b]) /
                                        mpmath.sqrt(mpmath.mpf(cov[a, a]) * mpmath.mpf(cov[b, b])))
-    M = corr if pca_on == "corr" else cov
-    if np.all(np.isfinite(M)):
-        lam, vec = eig_sym(M)
-        tot = float(sum(Fraction(float(x)) for x in lam))
-        var_pct = 100.0 * lam / tot
-        cum_pct = np.cumsum(var_pct)
-    else:
-        lam = np.full(q, np.nan)
-        vec = np.full((q, q), np.nan)
-        var_pct = np.full(q, np.nan)
-        cum_pct = np.full(q, np.nan)
+    lam, vec, var_pct, cum_pct = pca(corr if pca_on == "corr" else cov)
     return {"mean": mean, "cov": cov, "corr": corr, "eigval": lam, "eigvec": vec,
             "var_pct": var_pct, "cum_pct": cum_pct}
+
+
+def pca(M):
+    """Principal components of a symmetric matrix (section "Principal
+    Component Analysis Results", Table 3's columns): eigenvalues descending,
+    eigenvector rows (sign rule of ``eig_sym``), the share of each eigenvalue
+    in their sum as a percentage, var%_k = 100 lambda_k / sum(lambda), and
+    its running sum cum%_k.  All NaN when M has a non-finite entry."""
+    M = np.asarray(M, dtype=np.float64)
+    q = M.shape[0]
+    if not np.all(np.isfinite(M)):
+        nan = np.full(q, np.nan)
+        return nan, np.full((q, q), np.nan), nan.copy(), nan.copy()
+    lam, vec = eig_sym(M)
+    tot = float(sum(Fraction(float(x)) for x in lam))
+    var_pct = 100.0 * lam / tot
+    cum_pct = np.cumsum(var_pct)
+    return lam, vec, var_pct, cum_pct
 
 
 # ---- exact brute force (tiny inputs) -----------------------------------------
@@ -345,5 +422,6 @@ def sqrt_fraction(x: Fraction, digits: int = 60):
         return mpmath.sqrt(mpmath.mpf(x.numerator) / x.denominator)
 
 
-__all__ = ["OracleStats", "sufficient_stats", "sufficient_stats_stream", "finalize", "eig_sym",
+__all__ = ["OracleStats", "sufficient_stats", "sufficient_stats_stream", "integer_sums", "finalize",
+           "pca", "eig_sym",
            "brute_force", "parse_csv", "tri_index", "columns_of", "build"]

@@ -150,6 +150,37 @@ int oracle_pass1(const oc_col* cols, int32_t p, int64_t r0, int64_t r1, uint64_t
   return bad;
 }
 
+/* Exact pass over rows [r0, r1) for integer-valued columns only: the sums
+ * and cross products of the definition (section "Data Representation and
+ * Sufficient Statistics"), in __int128, nothing else.  Same output layout as
+ * the integer part of oracle_pass1 (two int64 halves per entry, packed upper
+ * triangle).  Returns 0, or 1 if a column holds a non-integer value. */
+int oracle_pass_int(const oc_col* cols, int32_t p, int64_t r0, int64_t r1, uint64_t* s_int,
+                    uint64_t* C_int) {
+  const int64_t T = (int64_t)p * (p + 1) / 2;
+  i128* si = (i128*)calloc((size_t)p, sizeof(i128));
+  i128* ci = (i128*)calloc((size_t)T, sizeof(i128));
+  i128* xi = (i128*)calloc((size_t)p, sizeof(i128));
+  int32_t bad = 0;
+  for (int64_t r = r0; r < r1; ++r) {
+    for (int i = 0; i < p; ++i) xi[i] = get_int(&cols[i], r, &bad);
+    for (int i = 0; i < p; ++i) {
+      si[i] += xi[i];
+      for (int j = i; j < p; ++j) ci[tri(p, i, j)] += xi[i] * xi[j];
+    }
+  }
+  for (int i = 0; i < p; ++i) {
+    s_int[2 * i] = (uint64_t)si[i];
+    s_int[2 * i + 1] = (uint64_t)(si[i] >> 64);
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    C_int[2 * t] = (uint64_t)ci[t];
+    C_int[2 * t + 1] = (uint64_t)(ci[t] >> 64);
+  }
+  free(si); free(ci); free(xi);
+  return bad;
+}
+
 /* Pass 2 over rows [r0, r1): compensated (hi, lo) of the centred products
  * sum (x_i - mu_i)(x_j - mu_j) for every pair, where each difference is
  * itself kept exactly as a TwoSum pair. */

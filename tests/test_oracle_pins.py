@@ -26,14 +26,91 @@ def test_table2_eigenvalues_match_table3():
 
 
 def test_table2_variance_and_cumulative_percent_match_table3():
-    A = table2()
-    st_like = A  # PCA input is the printed correlation matrix itself
-    lam, _ = oracle.eig_sym(st_like)
-    var = 100.0 * lam / lam.sum()
-    cum = np.cumsum(var)
+    # the oracle's own PCA stage (the one finalize uses) on the printed
+    # correlation matrix: every printed column of Table 3
+    lam, vec, var, cum = oracle.pca(table2())
     t3 = table3()
+    assert [_six(x) for x in lam] == [float(s) for s in t3["eig_str"]]
     assert [_six(x) for x in var] == [float(s) for s in t3["var_str"]]
     assert [_six(x) for x in cum] == [float(s) for s in t3["cum_str"]]
+    L = t3["loadings"]
+    for k in range(10):
+        s = 1.0 if vec[k] @ L[k] > 0 else -1.0
+        assert np.max(np.abs(s * vec[k] - L[k])) <= 5.1e-7, k
+
+
+def _factorial_design(amps, offsets, reps):
+    """Rows of a full two-level factorial design: column i is
+    offsets[i] + amps[i] * (+-1) over every sign pattern, repeated reps
+    times.  Distinct columns are exactly uncorrelated (every product of two
+    different sign columns sums to zero), so the sample covariance is
+    diag(amps^2 n / (n - 1)) exactly."""
+    p = len(amps)
+    signs = np.array([[1.0 if (r >> i) & 1 else -1.0 for i in range(p)] for r in range(1 << p)])
+    x = np.tile(signs, (reps, 1)) * np.asarray(amps) + np.asarray(offsets)
+    return x
+
+
+def test_cov_pca_variance_percent_closed_form():
+    # PCA of a diagonal covariance: eigenvalues are the variances (sorted),
+    # eigenvectors the unit vectors, var% = 100 a_k^2 / sum(a^2); the sum of
+    # the eigenvalues is not p, so a variance share taken over p fails here
+    amps = [1.0, 3.0, 0.5, 2.0]
+    offs = [1000.25, -7.5, 3.0e4, 0.125]
+    x = _factorial_design(amps, offs, 3)
+    n = x.shape[0]
+    st = oracle.sufficient_stats(oracle.columns_of(x), [False] * 4)
+    f = oracle.finalize(st, pca_on="cov")
+    order = [1, 3, 0, 2]
+    a2 = np.array(amps) ** 2
+    assert [float(v) for v in f["eigval"]] == [float(Fraction(a2[k]) * n / (n - 1)) for k in order]
+    for r, k in enumerate(order):
+        e = np.zeros(4)
+        e[k] = 1.0
+        assert np.array_equal(np.abs(f["eigvec"][r]), e) and f["eigvec"][r][k] == 1.0
+    tot = a2.sum()
+    assert np.allclose(f["var_pct"], [100.0 * a2[k] / tot for k in order], rtol=1e-15, atol=0)
+    assert np.allclose(f["cum_pct"], np.cumsum([100.0 * a2[k] / tot for k in order]), rtol=1e-15, atol=0)
+    assert f["mean"].tolist() == offs
+    # PCA of the correlation matrix of the same rows: the identity
+    fc = oracle.finalize(st)
+    assert np.array_equal(fc["corr"], np.eye(4))
+    assert fc["eigval"].tolist() == [1.0] * 4
+    assert fc["var_pct"].tolist() == [25.0] * 4 and fc["cum_pct"].tolist() == [25.0, 50.0, 75.0, 100.0]
+
+
+def _householder_q(p, seed, nrefl=3):
+    """An orthogonal matrix: a product of Householder reflections."""
+    rng = np.random.default_rng(seed)
+    Q = np.eye(p)
+    for _ in range(nrefl):
+        v = rng.standard_normal(p)
+        Q = Q - 2.0 * np.outer(Q @ v, v) / (v @ v)
+    return Q
+
+
+@pytest.mark.parametrize("p", [12, 40, 257])
+def test_eig_sym_known_eigenpairs(p):
+    # A = Q^T diag(lam) Q: the rows of Q are its eigenvectors.  The
+    # eigenvalues are a shuffled 1..p, so the order, the orientation of the
+    # returned vectors (rows, not columns) and the sign rule are all checked;
+    # p = 12 takes the 50-digit branch, 40 and 257 the LAPACK branch
+    Q = _householder_q(p, p)
+    lam_true = np.random.default_rng(100 + p).permutation(np.arange(1.0, p + 1.0))
+    A = Q.T @ np.diag(lam_true) @ Q
+    A = 0.5 * (A + A.T)
+    lam, vec = oracle.eig_sym(A)
+    assert np.max(np.abs(lam - np.arange(p, 0, -1.0))) <= 1e-12 * p
+    for k in range(p):
+        src = int(np.argmax(lam_true == p - k))
+        want = Q[src] if Q[src][np.argmax(np.abs(Q[src]))] > 0 else -Q[src]
+        assert np.max(np.abs(vec[k] - want)) <= 1e-12, k
+        j = int(np.argmax(np.abs(vec[k])))
+        assert vec[k][j] > 0
+    lam2, vec2, var, cum = oracle.pca(A)
+    assert np.array_equal(lam2, lam) and np.array_equal(vec2, vec)
+    assert np.allclose(var, 100.0 * np.arange(p, 0, -1.0) / (p * (p + 1) / 2), rtol=1e-12, atol=0)
+    assert abs(cum[-1] - 100.0) <= 1e-12
 
 
 def test_table2_loadings_match_table3_rows_up_to_sign():
@@ -120,8 +197,17 @@ def test_oracle_matches_exact_rationals(seed, n):
             # sqrt(M2_ii M2_jj), which bounds sum |centred products|
             scale = float(abs(ex["M2"][i][i] * ex["M2"][j][j])) ** 0.5
             assert abs(float(st.M2[t] - ex["M2"][i][j])) <= 1e-24 * scale + 1e-300
+    # means: integer columns correctly rounded, floating ones from the
+    # compensated sum (within one rounding of the exact mean)
+    for i in range(p):
+        exact_mean = ex["mean"][i]
+        if is_int[i]:
+            assert st.mu[i] == float(exact_mean)
+        else:
+            assert abs(st.mu[i] - float(exact_mean)) <= 1.2e-16 * abs(float(exact_mean))
     if n > 1:
         f = oracle.finalize(st)
+        assert f["mean"].tolist() == st.mu
         for i in range(p):
             for j in range(p):
                 exact = ex["cov"][i][j]
@@ -235,3 +321,34 @@ def test_csv_roundtrip_is_bit_exact():
 def test_csv_parse_rejects_garbage():
     with pytest.raises(ValueError):
         oracle.parse_csv(b"1,2,x\n", 3, [True, True, True])
+
+
+# ---- threads and the integer-only pass ----------------------------------------
+
+def test_threaded_passes_agree():
+    # row ranges reduced on several threads: the exact integer parts are
+    # identical, the compensated parts agree to far below one FP64 rounding
+    x = datagen.table1_aos(9, 10_007)
+    is_int = [True] * 8 + [False, True]
+    a = oracle.sufficient_stats(oracle.columns_of(x), is_int)
+    b = oracle.sufficient_stats(oracle.columns_of(x), is_int, threads=5)
+    assert a.n == b.n and a.s_int == b.s_int and a.C_int == b.C_int
+    for u, v in zip(a.s_exact + a.C_exact + a.M2, b.s_exact + b.C_exact + b.M2):
+        assert abs(u - v) <= Fraction(1, 10**22) * max(abs(u), 1)
+    fa = oracle.finalize(a, mask=range(1, 10))
+    fb = oracle.finalize(b, mask=range(1, 10))
+    assert np.array_equal(fa["cov"], fb["cov"]) and fa["mean"].tolist() == fb["mean"].tolist()
+
+
+def test_integer_sums_match_brute_force_and_closed_forms():
+    x = datagen.table1_aos(8, 3001)
+    cols = [x[:, c].astype(np.int64) for c in range(10) if c != 8]
+    n, s, C = oracle.integer_sums(cols, threads=3)
+    rows = [[int(v) for v in r] for r in np.stack(cols, axis=1)]
+    ex = oracle.brute_force(rows)
+    assert n == 3001
+    assert s == [int(v) for v in ex["s"]]
+    assert C == [int(ex["C"][i][j]) for i in range(9) for j in range(i, 9)]
+    assert s[0] == n * (n + 1) // 2 and C[0] == n * (n + 1) * (2 * n + 1) // 6
+    with pytest.raises(ValueError):
+        oracle.integer_sums([np.array([1.0, 2.5])])
