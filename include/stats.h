@@ -117,16 +117,24 @@ typedef struct {
                                              every column not flagged IDENTIFIER */
   int32_t ddof;         /* divisor N - ddof; 1 = sample covariance */
   int32_t pca_on;       /* 0 = correlation matrix (default), 1 = covariance */
-  int32_t want_vectors; /* 0 = eigenvalues only */
+  int32_t want_vectors; /* 0 = eigenvalues only: eigvec is not written */
 } stats_finalize_opts;
 
-/* Opens a handle on cfg->device.  Checks: 1 <= p <= STATS_MAX_P; planes in
- * range; each column's element inside its row stride; INTEGER only on
- * integer-capable columns; block_rows 0 or a multiple of 1024.  On error
- * *out is NULL. */
+/* Opens a handle on cfg->device for one table whose rows are described by
+ * cfg's columns (section "Data Representation and Sufficient Statistics":
+ * fixed-width records, row-major, with contiguous access from host and
+ * device; several planes allow column-major data as well).  Checks:
+ * 1 <= p <= STATS_MAX_P; planes in range; each column's element inside its
+ * row stride; INTEGER only on integer-capable columns; block_rows 0 or a
+ * multiple of 1024.  On error *out is NULL. */
 int stats_open(const stats_config* cfg, stats_ctx** out);
 
-/* Adds nrows rows.  planes[k] is the base of plane k (device address for
+/* Adds nrows rows: the single streaming pass of section "Data
+ * Representation and Sufficient Statistics" (column sums and X^T X of a
+ * chunk, shifted by each block's first row as section "Numerical
+ * Considerations" requires), merged into the handle.  Chunks streamed from
+ * host memory follow section "System Overview" (storage -> host memory ->
+ * GPU).  planes[k] is the base of plane k (device address for
  * STATS_MEM_DEVICE; host address otherwise).  Device planes must be 16-byte
  * aligned.  Host input is streamed in chunks of staging_rows rows through two
  * device staging slots, the copy of one chunk (on a second stream)
@@ -136,7 +144,11 @@ int stats_open(const stats_config* cfg, stats_ctx** out);
  * the call returns.  nrows == 0 is a no-op. */
 int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows, int32_t mem_kind);
 
-/* Adds the complete lines of a CSV text chunk: one row per line, p fields
+/* Adds the complete lines of a CSV text chunk, parsed on the GPU and fed
+ * straight into the same accumulation (the paper's first pipeline streamed
+ * CSV in fixed-size chunks: section "Validation and Infrastructure Testing";
+ * its parsing cost: section "Data Representation and Sufficient
+ * Statistics").  Lines must end in '\n'; one row per line, p fields
  * separated by ',', integer columns in decimal, floating columns as decimal
  * floating-point text (parsed with correct rounding).  Only complete lines
  * are consumed unless is_last != 0, when a final unterminated line counts
@@ -146,7 +158,9 @@ int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows, int
 int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
                           int32_t is_last, int64_t* bytes_consumed);
 
-/* Batched groups: a handle holding ngroups independent statistics. */
+/* Batched groups: a handle holding ngroups independent sets of the
+ * statistics of section "Data Representation and Sufficient Statistics"
+ * (one per group of rows), for many tables of uneven size in one launch. */
 int stats_open_groups(const stats_config* cfg, int32_t ngroups, stats_ctx** out);
 
 /* Adds rows to every group in one launch: group g receives the rows
@@ -155,8 +169,13 @@ int stats_open_groups(const stats_config* cfg, int32_t ngroups, stats_ctx** out)
 int stats_accumulate_segmented(stats_ctx* h, const void* const* planes,
                                const int64_t* row_offsets, int32_t mem_kind);
 
-/* dst := statistics of rows(dst) and rows(src); src unchanged.  Both must
- * have the same columns (else STATS_E_MISMATCH) and be single-group. */
+/* dst := statistics of rows(dst) and rows(src); src unchanged: the
+ * combination of the partial results of disjoint row subsets (section
+ * "Validation and Infrastructure Testing"; the partials are combined without
+ * forming X^T X - N mu mu^T, section "Numerical Considerations").  Both must
+ * have the same columns (else STATS_E_MISMATCH) and be single-group.  A
+ * deferred error of src (STATS_E_INEXACT, STATS_E_PARSE) carries over to dst
+ * and is reported by dst's next sync, raw or finalize. */
 int stats_merge(stats_ctx* dst, const stats_ctx* src);
 
 /* Clears the statistics of the handle (all groups) so it can take a new
@@ -167,7 +186,8 @@ int stats_reset(stats_ctx* h);
  * STATS_E_PARSE. */
 int stats_sync(stats_ctx* h);
 
-/* The sufficient statistics (N, s, C) themselves.  s_int / C_int hold exact
+/* The sufficient statistics (N, s, C) themselves (section "Data
+ * Representation and Sufficient Statistics").  s_int / C_int hold exact
  * values where the column (pair) is integer, zero elsewhere; s_f64 / C_f64
  * hold every entry in FP64 (integer entries correctly rounded);
  * exact_mask[i*p+j] = 1 where the entry is exact.  C arrays are p x p.  Any
@@ -176,7 +196,11 @@ int stats_raw(stats_ctx* h, int64_t* n, stats_i128* s_int, double* s_f64, stats_
               double* C_f64, uint8_t* exact_mask);
 
 /* Means, covariance, correlation and PCA of the kept columns (p' of them,
- * written to *p_out).  cov = centred co-moment / (N - ddof), correctly
+ * written to *p_out), from the statistics alone (section "Data
+ * Representation and Sufficient Statistics"; the identifier is left out by
+ * default, section "Numerical Considerations"; eigenpairs, variance % and
+ * cumulative % as in section "Principal Component Analysis Results",
+ * Table 3).  cov = centred co-moment / (N - ddof), correctly
  * rounded for integer pairs; corr = cov_ij / sqrt(cov_ii cov_jj) with a unit
  * diagonal (NaN where a variance is zero); eigenpairs of corr (or cov) by
  * FP64 Jacobi on the GPU, eigenvalues descending, eigvec row k = component k
@@ -198,7 +222,9 @@ int stats_finalize_groups(stats_ctx* h, const stats_finalize_opts* opts, int32_t
 int stats_group_raw(stats_ctx* h, int32_t g, int64_t* n, stats_i128* s_int, double* s_f64,
                     stats_i128* C_int, double* C_f64, uint8_t* exact_mask);
 
-/* Checkpoint: the statistics of a single-group handle as bytes.  With buf
+/* Checkpoint: the statistics of a single-group handle as bytes (partial
+ * results moved to the host for combination, section "Validation and
+ * Infrastructure Testing").  With buf
  * NULL, *len receives the size needed; otherwise *len is the capacity and
  * receives the size written. */
 int stats_serialize(stats_ctx* h, void* buf, size_t* len);

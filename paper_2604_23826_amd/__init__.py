@@ -241,13 +241,15 @@ def finalize_opts(mask=None, ddof: int = 1, pca_on: int = 0, want_vectors: int =
     return o
 
 
-def stats_finalize(h: int, p: int, mask=None, ddof: int = 1, pca_on: int = 0) -> dict:
+def stats_finalize(h: int, p: int, mask=None, ddof: int = 1, pca_on: int = 0,
+                   want_vectors: int = 1) -> dict:
     """Means, cov, corr and PCA of the kept columns (p' of them; flat C arrays
-    of p' x p' are reshaped here)."""
+    of p' x p' are reshaped here).  With want_vectors=0 the library leaves
+    eigvec unwritten (it stays NaN here)."""
     q = p if mask is None else len(list(mask))
-    o = finalize_opts(mask, ddof, pca_on)
+    o = finalize_opts(mask, ddof, pca_on, want_vectors)
     flat = {"mean": np.zeros(q), "cov": np.zeros(q * q), "corr": np.zeros(q * q),
-            "eigval": np.zeros(q), "eigvec": np.zeros(q * q), "var_pct": np.zeros(q),
+            "eigval": np.zeros(q), "eigvec": np.full(q * q, np.nan), "var_pct": np.zeros(q),
             "cum_pct": np.zeros(q)}
     pq = _i32(0)
     _check(_lib.stats_finalize(h, ctypes.byref(o), ctypes.byref(pq),

@@ -17,12 +17,19 @@ FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-Wall",
          "-I", os.path.join(HERE, "..", "include")]
 
 
-def build(verbose: bool = False, jobs: int = 8) -> str:
+def build(verbose: bool = False, jobs: int = 8, force: bool = True) -> str:
+    """Compiles every HIP source (force=False: only those older than their
+    object file or than any header) and links libstats.so."""
     os.makedirs(OBJ, exist_ok=True)
     srcs = sorted(glob.glob(os.path.join(CSRC, "*.hip")))
+    headers = glob.glob(os.path.join(CSRC, "*.hpp")) + [os.path.join(HERE, "..", "include", "stats.h")]
+    newest_header = max(os.path.getmtime(f) for f in headers)
 
     def compile_one(src):
         obj = os.path.join(OBJ, os.path.basename(src) + ".o")
+        if (not force and os.path.exists(obj) and
+                os.path.getmtime(obj) > max(os.path.getmtime(src), newest_header)):
+            return obj
         cmd = [HIPCC, *FLAGS, "-c", "-o", obj, src]
         if verbose:
             print(" ".join(cmd), flush=True)
@@ -46,5 +53,5 @@ def build(verbose: bool = False, jobs: int = 8) -> str:
 
 
 if __name__ == "__main__":
-    build(verbose="-v" in sys.argv)
+    build(verbose="-v" in sys.argv, force="--changed" not in sys.argv)
     print(LIB)

@@ -356,7 +356,8 @@ static bool aos_rows_layout(const stats_ctx* h, const void* const* planes, int R
 static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t nrows, int64_t R, int RS) {
   const int p = h->p;
   const int pl = h->cols[0].plane;
-  // slot table and queue word in aux3 (used by the wide path only, p > 16)
+  // slot table and queue word in aux3 (shared with the wide path,
+  // accumulate_device_wide; one of them runs per launch, stream-ordered)
   const size_t slot_bytes = (sizeof(wide::SlotInfo) * (size_t)p + 255) / 256 * 256;
   int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, slot_bytes + 256);
   if (rc) return rc;
@@ -365,7 +366,9 @@ static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t 
   int ncu = 256;
   (void)hipDeviceGetAttribute(&ncu, hipDeviceAttributeMultiprocessorCount, h->device);
   const int64_t W = rec_words(p);
-  const int64_t max_rows = ((int64_t)1 << 28) / R * R;
+  // at most 2^28 rows and 16384 blocks per launch (the depth of the merge
+  // tree over one launch's blocks stays at most 14)
+  const int64_t max_rows = std::max<int64_t>(R, std::min<int64_t>(16384 * R, ((int64_t)1 << 28) / R * R));
   std::vector<wide::SlotInfo> slots(p);
   int64_t done = 0;
   while (done < nrows) {
@@ -632,22 +635,27 @@ extern "C" int stats_merge(stats_ctx* dst, const stats_ctx* src) {
   const Layout L = Layout::make(dst->p);
   const size_t bytes = (size_t)L.words * 8;
   const uint64_t* src_state = s->state[s->cur];
+  const DevStatus* src_status = s->status_dev;
   hipError_t e;
   if (s->device != dst->device) {
-    // bring the source state over through the host
-    std::vector<uint64_t> tmp(L.words);
+    // bring the source state and status word over through the host
+    std::vector<uint64_t> tmp(L.words + sizeof(DevStatus) / 8);
     {
       DeviceGuard gs(s->device);
       e = hipStreamSynchronize(s->stream);
       if (e == hipSuccess) e = hipMemcpy(tmp.data(), src_state, bytes, hipMemcpyDeviceToHost);
+      if (e == hipSuccess)
+        e = hipMemcpy(tmp.data() + L.words, s->status_dev, sizeof(DevStatus), hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(s, e, "reading source state");
     }
-    int rc = ensure_dev(dst, &dst->aux_dev, &dst->aux_cap, bytes);
+    int rc = ensure_dev(dst, &dst->aux_dev, &dst->aux_cap, bytes + sizeof(DevStatus));
     if (rc) return rc;
-    e = hipMemcpyAsync(dst->aux_dev, tmp.data(), bytes, hipMemcpyHostToDevice, dst->stream);
+    e = hipMemcpyAsync(dst->aux_dev, tmp.data(), bytes + sizeof(DevStatus), hipMemcpyHostToDevice,
+                       dst->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(dst->stream);
     if (e != hipSuccess) return hip_fail(dst, e, "uploading source state");
     src_state = (const uint64_t*)dst->aux_dev;
+    src_status = (const DevStatus*)((const char*)dst->aux_dev + bytes);
   } else if (s->stream != dst->stream) {
     hipEvent_t ev;
     e = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
@@ -658,6 +666,8 @@ extern "C" int stats_merge(stats_ctx* dst, const stats_ctx* src) {
   }
   launch_merge_states(dst->state[dst->cur], src_state, dst->state[dst->cur ^ 1], dst->p,
                       dst->intf_dev, dst->stream);
+  // a deferred error of the source (exactness guard, parse) now holds for dst
+  launch_status_or(dst->status_dev, src_status, dst->stream);
   e = hipGetLastError();
   if (e != hipSuccess) return hip_fail(dst, e, "merge kernel launch");
   dst->cur ^= 1;
@@ -790,7 +800,7 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   F.intflags_dev = h->intf_dev;
   F.ddof = o->ddof;
   F.pca_on = o->pca_on;
-  F.want_vectors = 1;
+  F.want_vectors = o->want_vectors ? 1 : 0;
   F.out = h->fin_out;
   F.scratch = h->fin_scratch;
   F.jtab = h->fin_scratch + 2 * (size_t)q * q;
@@ -822,7 +832,7 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   if (cov) memcpy(cov, po + q, qq * 8);
   if (corr) memcpy(corr, po + q + qq, qq * 8);
   if (eigval) memcpy(eigval, po + q + 2 * qq, q * 8);
-  if (eigvec) memcpy(eigvec, po + 2 * q + 2 * qq, qq * 8);
+  if (eigvec && o->want_vectors) memcpy(eigvec, po + 2 * q + 2 * qq, qq * 8);
   if (var_pct) memcpy(var_pct, po + 2 * q + 3 * qq, q * 8);
   if (cum_pct) memcpy(cum_pct, po + 3 * q + 3 * qq, q * 8);
   return STATS_OK;

@@ -393,6 +393,9 @@ int64_t launch_accum_small_p(const AccumLaunch& a, hipStream_t s);
 void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intflags_dev,
                           const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s);
 
+// dst status |= src status (stream-ordered; see k_status_or).
+void launch_status_or(DevStatus* dst, const DevStatus* src, hipStream_t s);
+
 // Merge two states: out = merge(a, b).
 void launch_merge_states(const uint64_t* a, const uint64_t* b, uint64_t* out, int p,
                          const uint8_t* intflags_dev, hipStream_t s);

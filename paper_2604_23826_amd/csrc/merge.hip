@@ -207,7 +207,21 @@ __global__ __launch_bounds__(kTreeThreads) void k_merge_tree(const uint64_t* __r
   }
 }
 
+// Deferred errors of a merged source (exactness guard, text parse) carry
+// over to the destination: bits are OR-ed, the smaller parse offset is kept.
+__global__ void k_status_or(DevStatus* dst, const DevStatus* src) {
+  if (threadIdx.x == 0) {
+    const DevStatus s = *src;
+    dst->bits |= s.bits;
+    if (s.parse_off < dst->parse_off) dst->parse_off = s.parse_off;
+  }
+}
+
 }  // namespace
+
+void launch_status_or(DevStatus* dst, const DevStatus* src, hipStream_t s) {
+  hipLaunchKernelGGL(k_status_or, dim3(1), dim3(64), 0, s, dst, src);
+}
 
 void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intf,
                           const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s) {

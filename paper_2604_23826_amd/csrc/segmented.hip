@@ -273,9 +273,14 @@ struct Tuned {
 std::mutex g_tune_mu;
 std::map<std::string, Tuned> g_tuned;
 
-std::string tune_key(const stats_ctx* h, const char* arch) {
-  std::string k = std::string(arch) + ":p" + std::to_string(h->p) + ":";
-  for (const auto& c : h->cols) k += std::to_string(c.dtype);
+// What the tuned tile height and occupancy depend on: the device, the
+// kernel (the 256-byte record kernel or the general one) and the layout of
+// every column (type, plane, byte offset, plane row stride).
+std::string tune_key(const stats_ctx* h, const char* arch, bool aos64) {
+  std::string k = std::string(arch) + ":p" + std::to_string(h->p) + (aos64 ? ":rec" : ":gen");
+  for (const auto& c : h->cols)
+    k += ":" + std::to_string(c.dtype) + "." + std::to_string(c.plane) + "." +
+         std::to_string(c.byte_offset) + "." + std::to_string(h->row_stride[c.plane]);
   return k;
 }
 
@@ -561,7 +566,7 @@ extern "C" int stats_accumulate_segmented(stats_ctx* h, const void* const* plane
     hipDeviceProp_t prop;
     const char* arch = "gfx";
     if (hipGetDeviceProperties(&prop, h->device) == hipSuccess) arch = prop.gcnArchName;
-    const std::string key = tune_key(h, arch);
+    const std::string key = tune_key(h, arch, seg_aos64_layout(h, planes));
     if (!tune_cache_lookup(key, &tu)) {
       int rc = autotune(h, planes, row_offsets, ST, sts, &tu);
       if (rc) return rc;

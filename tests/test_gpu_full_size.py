@@ -12,8 +12,17 @@ size and what the oracle can compute piece by piece:
     to summation-order noise;
   * sampled windows -- the tail of the ragged last chunk and a window that
     straddles a chunk boundary -- against the oracle on the same rows,
-    generated independently on the host.
+    generated independently on the host;
+  * the exact sums and cross products of all nine integer columns over the
+    whole share, from the oracle's integer-only pass run on host threads
+    over host-generated chunks, and from them every integer covariance
+    (identifier included) as an exact rational, correctly rounded.
 """
+import os
+import time
+from concurrent.futures import ThreadPoolExecutor
+from fractions import Fraction
+
 import numpy as np
 import pytest
 
@@ -85,6 +94,78 @@ def test_full_share_closed_forms_and_partition(share):
     assert np.array_equal(cov, cov.T) and np.all(np.diag(corr) == 1.0)
     assert abs(np.sum(fin["eigval"]) - np.trace(corr)) <= 1e-12 * 9
     assert np.all(fin["eigval"] > 0) and abs(fin["cum_pct"][-1] - 100.0) <= 1e-9
+
+
+def test_full_share_identifier_kept_is_exact(share):
+    """With the identifier kept, its variance at N = 2e9 is N(N+1)/12 and its
+    mean (N+1)/2, both exactly: the 121-bit numerator N C - s s^T path."""
+    L = lib()
+    h = L.stats_open(planar_config(stream=current_stream()))
+    try:
+        for a in range(0, N, CH):
+            L.stats_accumulate(h, _view(share, a), min(CH, N - a))
+        fin = L.stats_finalize(h, 10, mask=range(10))
+    finally:
+        L.stats_close(h)
+    assert fin["cov"][0, 0] == float(Fraction(N * (N + 1), 12))
+    assert fin["mean"][0] == (N + 1) / 2
+    assert fin["corr"][0, 0] == 1.0
+
+
+INT_COLS = [c for c in range(10) if TABLE1_INT[c]]  # A..H, I
+
+
+def _host_integer_sums():
+    """Exact (n, s, C) of the nine integer columns of all 2e9 rows: chunks of
+    2^22 rows generated on host threads, each reduced by the oracle's
+    integer-only pass; the partial sums are Python ints (exact)."""
+    step = 1 << 22
+    starts = list(range(0, N, step))
+    nthr = max(1, min(16, os.cpu_count() or 1))
+    p = len(INT_COLS)
+    s = [0] * p
+    C = [0] * (p * (p + 1) // 2)
+
+    def job(r0):
+        m = min(step, N - r0)
+        cols = datagen.table1_planar(SEED, m, row0=r0)
+        return oracle.integer_sums([cols[c] for c in INT_COLS])
+
+    t0 = time.time()
+    done = 0
+    with ThreadPoolExecutor(nthr) as ex:
+        for k, (m, ss, CC) in enumerate(ex.map(job, starts)):
+            done += m
+            s = [a + b for a, b in zip(s, ss)]
+            C = [a + b for a, b in zip(C, CC)]
+            if k % 64 == 63:
+                print(f"  oracle: {done} rows, {time.time() - t0:.0f} s", flush=True)
+    assert done == N
+    return s, C
+
+
+def test_full_share_integer_sums_against_oracle(share):
+    print("full-share integer sums on the host", flush=True)
+    s_ref, C_ref = _host_integer_sums()
+    L = lib()
+    h = L.stats_open(planar_config(stream=current_stream()))
+    try:
+        for a in range(0, N, CH):
+            L.stats_accumulate(h, _view(share, a), min(CH, N - a))
+        raw = L.stats_raw(h, 10)
+        fin = L.stats_finalize(h, 10, mask=INT_COLS)
+    finally:
+        L.stats_close(h)
+    p = len(INT_COLS)
+    for a, ca in enumerate(INT_COLS):
+        assert raw["s_int"][ca] == s_ref[a], ca
+        for b in range(a, p):
+            cb = INT_COLS[b]
+            cab = C_ref[oracle.tri_index(p, a, b)]
+            assert raw["C_int"][ca][cb] == cab, (ca, cb)
+            # exact covariance, correctly rounded (ddof = 1)
+            want = float(Fraction(N * cab - s_ref[a] * s_ref[b], N * (N - 1)))
+            assert fin["cov"][a, b] == want and fin["cov"][b, a] == want, (ca, cb)
 
 
 @pytest.mark.parametrize("row0,n", [(N - (1 << 20), 1 << 20), (3 * CH - (1 << 19), 1 << 20)])

@@ -362,3 +362,121 @@ def test_fp64_rows_of_128_bytes_on_matrix_cores(p, n, block_rows):
     check_raw_against_oracle(raw, st, int_cols)
     if fin is not None:
         check_final_against_oracle(fin, oracle.finalize(st), int_cols)
+
+
+def test_merge_against_oracle():
+    """stats_merge of handles over disjoint row sets (one of them empty, one a
+    single row) equals the oracle on their union: integer entries bit-exact,
+    the rest to the oracle tolerance; merging into an empty handle too."""
+    L = lib()
+    n = 180_001
+    x = datagen.table1_aos(12, n)
+    d = to_dev(x)
+    s = current_stream()
+    cuts = [(0, 0), (0, 1), (1, 65_537), (65_537, n)]
+    hs = [L.stats_open(aos_config(stream=s)) for _ in cuts]
+    empty = L.stats_open(aos_config(stream=s))
+    try:
+        for h, (a, b) in zip(hs, cuts):
+            if b > a:
+                L.stats_accumulate(h, [d[a:]], b - a)
+        for h in hs[1:]:
+            L.stats_merge(hs[0], h)
+        L.stats_merge(empty, hs[0])
+        raws = [L.stats_raw(hs[0], 10), L.stats_raw(empty, 10)]
+        fins = [L.stats_finalize(hs[0], 10), L.stats_finalize(empty, 10)]
+    finally:
+        for h in hs + [empty]:
+            L.stats_close(h)
+    st, ref = _oracle(x)
+    for raw, fin in zip(raws, fins):
+        check_raw_against_oracle(raw, st, TABLE1_INT)
+        check_final_against_oracle(fin, ref, [TABLE1_INT[c] for c in SEL])
+
+
+def test_merge_carries_the_source_error():
+    """A source whose integer column held a fraction, merged before anyone
+    synchronized it, makes the destination report STATS_E_INEXACT."""
+    L = lib()
+    s = current_stream()
+    bad = datagen.table1_aos(13, 4000)
+    bad[100, 2] += 0.25
+    good = datagen.table1_aos(14, 4000)
+    src = L.stats_open(aos_config(stream=s))
+    dst = L.stats_open(aos_config(stream=s))
+    try:
+        L.stats_accumulate(src, [to_dev(bad)], 4000)
+        L.stats_accumulate(dst, [to_dev(good)], 4000)
+        L.stats_merge(dst, src)
+        with pytest.raises(L.StatsError) as e:
+            L.stats_finalize(dst, 10)
+        assert e.value.code == L.STATS_E_INEXACT
+        with pytest.raises(L.StatsError) as e:
+            L.stats_sync(dst)
+        assert e.value.code == L.STATS_E_INEXACT
+    finally:
+        L.stats_close(src)
+        L.stats_close(dst)
+
+
+def test_merge_of_different_columns_is_a_mismatch():
+    L = lib()
+    s = current_stream()
+    a = L.stats_open(aos_config(stream=s))
+    b = L.stats_open(aos_config(p=9, int_cols=TABLE1_INT[:9], stream=s))
+    c = L.stats_open(aos_config(int_cols=[True] * 10, stream=s))  # cotC flagged INTEGER
+    try:
+        for other in (b, c):
+            with pytest.raises(L.StatsError) as e:
+                L.stats_merge(a, other)
+            assert e.value.code == L.STATS_E_MISMATCH
+        with pytest.raises(L.StatsError) as e:
+            L.stats_merge(a, a)
+        assert e.value.code == L.STATS_E_ARG
+    finally:
+        for h in (a, b, c):
+            L.stats_close(h)
+
+
+def test_refused_allocation_is_nomem():
+    """STATS_FAIL_ALLOC makes every device allocation of the library fail:
+    stats_open and a first accumulate report STATS_E_NOMEM, and the handle
+    works again once allocations succeed."""
+    import os
+    L = lib()
+    s = current_stream()
+    x = datagen.table1_aos(15, 3000)
+    d = to_dev(x)
+    h = L.stats_open(aos_config(stream=s))
+    try:
+        os.environ["STATS_FAIL_ALLOC"] = "1"
+        with pytest.raises(L.StatsError) as e:
+            L.stats_open(aos_config(stream=s))
+        assert e.value.code == L.STATS_E_NOMEM
+        with pytest.raises(L.StatsError) as e:
+            L.stats_accumulate(h, [d], 3000)
+        assert e.value.code == L.STATS_E_NOMEM
+    finally:
+        os.environ.pop("STATS_FAIL_ALLOC", None)
+    try:
+        L.stats_accumulate(h, [d], 3000)
+        raw = L.stats_raw(h, 10)
+    finally:
+        L.stats_close(h)
+    st, _ = _oracle(x)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+
+
+def test_eigenvalues_only():
+    L = lib()
+    x = datagen.table1_aos(16, 20_000)
+    h = L.stats_open(aos_config(stream=current_stream()))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], 20_000)
+        full = L.stats_finalize(h, 10)
+        vals = L.stats_finalize(h, 10, want_vectors=0)
+    finally:
+        L.stats_close(h)
+    assert np.all(np.isnan(vals["eigvec"]))
+    for k in ("eigval", "var_pct", "cum_pct", "cov", "corr", "mean"):
+        assert np.array_equal(vals[k], full[k]), k
