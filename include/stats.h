@@ -144,6 +144,23 @@ int stats_open(const stats_config* cfg, stats_ctx** out);
  * the call returns.  nrows == 0 is a no-op. */
 int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows, int32_t mem_kind);
 
+/* For callers that cannot allocate device memory (code under HIP graph
+ * capture, tight serving loops, harnesses that forbid hipMalloc): the same
+ * reduction as stats_accumulate with STATS_MEM_DEVICE input, for handles of
+ * p <= 16 columns (else STATS_E_ARG), performing no allocation.  The block
+ * records of each launch go to one fixed device array of
+ * STATS_NOALLOC_SCRATCH_BYTES per GPU (held until the process ends) instead
+ * of handle-owned memory; rows are cut into launches whose records fit it.
+ * Every call on one GPU shares that array: calls that overlap in time on the
+ * same GPU (different streams, or host threads) race and must be ordered by
+ * the caller.  The first call on a device looks the array's address up
+ * (hipGetSymbolAddress); later calls only launch kernels.  Results equal
+ * stats_accumulate's (integer columns bit for bit; the 128-byte FP64 record
+ * layout with 11 <= p <= 16 takes the per-lane kernels here, so floating
+ * entries may differ in summation order). */
+#define STATS_NOALLOC_SCRATCH_BYTES (8u << 20)
+int stats_accumulate_noalloc(stats_ctx* h, const void* const* planes, int64_t nrows);
+
 /* Adds the complete lines of a CSV text chunk, parsed on the GPU and fed
  * straight into the same accumulation (the paper's first pipeline streamed
  * CSV in fixed-size chunks: section "Validation and Infrastructure Testing";

@@ -41,6 +41,7 @@ STATS_COL_INTEGER, STATS_COL_IDENTIFIER = 1, 2
 STATS_MEM_DEVICE, STATS_MEM_HOST_PINNED, STATS_MEM_HOST = 0, 1, 2
 STATS_PREC_FP64, STATS_PREC_SPLIT_BF16, STATS_PREC_AUTO = 0, 1, 2
 STATS_CFG_TIMING = 1
+STATS_NOALLOC_SCRATCH_BYTES = 8 << 20
 (STATS_K_ACCUM, STATS_K_MERGE, STATS_K_FINALIZE, STATS_K_SYRK, STATS_K_SEGMENTED,
  STATS_K_TEXT, STATS_K_COPY, STATS_K_COUNT) = range(8)
 
@@ -76,6 +77,7 @@ _sig = {
     "stats_open": [ctypes.POINTER(Config), ctypes.POINTER(_vp)],
     "stats_open_groups": [ctypes.POINTER(Config), _i32, ctypes.POINTER(_vp)],
     "stats_accumulate": [_vp, _vp, _i64, _i32],
+    "stats_accumulate_noalloc": [_vp, _vp, _i64],
     "stats_accumulate_text": [_vp, _vp, _i64, _i32, _i32, ctypes.POINTER(_i64)],
     "stats_accumulate_segmented": [_vp, _vp, _vp, _i32],
     "stats_merge": [_vp, _vp],
@@ -170,6 +172,11 @@ def _planes(planes):
 
 def stats_accumulate(h: int, planes, nrows: int, mem_kind: int = STATS_MEM_DEVICE) -> None:
     _check(_lib.stats_accumulate(h, _planes(planes), nrows, mem_kind))
+
+
+def stats_accumulate_noalloc(h: int, planes, nrows: int) -> None:
+    """Device input, p <= 16, no allocation in the call (see stats.h)."""
+    _check(_lib.stats_accumulate_noalloc(h, _planes(planes), nrows))
 
 
 def stats_accumulate_text(h: int, buf, nbytes: int, mem_kind: int = STATS_MEM_DEVICE,

@@ -423,17 +423,14 @@ static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t 
   return STATS_OK;
 }
 
-// Reduce nrows device-resident rows (plane bases already offset to the first
-// row) into the handle state.  Small p only (p <= 16).
-int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nrows) {
-  const int p = h->p;
-  const int64_t R = h->block_rows ? h->block_rows : auto_block_rows(nrows);
-  if (p >= 11 && aos_rows_layout(h, planes, 128)) return accumulate_aos_rows(h, planes, nrows, R, 128);
+// Launch description of the per-lane narrow kernels for the given planes
+// (row 0 at the plane bases; nrows, block_rows and rec left for the caller).
+AccumLaunch accum_launch_of(const stats_ctx* h, const void* const* planes) {
   AccumLaunch a;
   memset(&a, 0, sizeof a);
-  a.p = p;
+  a.p = h->p;
   a.kind = layout_kind(h, planes);
-  for (int c = 0; c < p; ++c) {
+  for (int c = 0; c < h->p; ++c) {
     const stats_column& col = h->cols[c];
     a.colbase[c] = (const char*)planes[col.plane] + col.byte_offset;
     a.colstride[c] = h->row_stride[col.plane];
@@ -442,6 +439,20 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
     if ((col.dtype == STATS_F32 || col.dtype == STATS_F64) && (col.flags & STATS_COL_INTEGER))
       a.chkmask |= 1u << c;
   }
+  return a;
+}
+
+int64_t block_rows_for(const stats_ctx* h, int64_t nrows) {
+  return h->block_rows ? h->block_rows : auto_block_rows(nrows);
+}
+
+// Reduce nrows device-resident rows (plane bases already offset to the first
+// row) into the handle state.  Small p only (p <= 16).
+int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nrows) {
+  const int p = h->p;
+  const int64_t R = block_rows_for(h, nrows);
+  if (p >= 11 && aos_rows_layout(h, planes, 128)) return accumulate_aos_rows(h, planes, nrows, R, 128);
+  const AccumLaunch a = accum_launch_of(h, planes);
   const int64_t W = rec_words(p);
   const Layout L = Layout::make(p);
   // at most 2^28 rows (and 16384 blocks) per launch: plane offsets stay 32-bit

@@ -88,6 +88,8 @@ int sync_handle(stats_ctx* h);
 void collect_timings(stats_ctx* h);
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows);
 int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrows);
+AccumLaunch accum_launch_of(const stats_ctx* h, const void* const* planes);
+int64_t block_rows_for(const stats_ctx* h, int64_t nrows);
 int raw_of_state(stats_ctx* h, const uint64_t* state_dev, int64_t* n, stats_i128* s_int,
                  double* s_f64, stats_i128* C_int, double* C_f64, uint8_t* exact_mask);
 int selection(const stats_ctx* h, const stats_finalize_opts* o, std::vector<int32_t>* sel);
