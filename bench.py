@@ -101,6 +101,78 @@ def cov_err(a, b):
     return float(np.max(np.abs(a - b) / s))
 
 
+def pinned_h2d_peak(torch, nbytes=1 << 30, reps=5):
+    """Best host-to-device rate of one plain copy from page-locked memory."""
+    src = torch.empty(nbytes, dtype=torch.uint8, pin_memory=True)
+    dst = torch.empty(nbytes, dtype=torch.uint8, device="cuda:0")
+    best = 0.0
+    for _ in range(reps):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        dst.copy_(src, non_blocking=True)
+        e1.record()
+        e1.synchronize()
+        best = max(best, nbytes / (e0.elapsed_time(e1) / 1e3) / 1e9)
+    return best
+
+
+def host_info():
+    """CPU model, hardware threads, threads this process may run on, RAM."""
+    model = None
+    try:
+        with open("/proc/cpuinfo") as f:
+            for ln in f:
+                if ln.startswith("model name"):
+                    model = ln.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    mem_gb = None
+    try:
+        with open("/proc/meminfo") as f:
+            for ln in f:
+                if ln.startswith("MemTotal"):
+                    mem_gb = round(int(ln.split()[1]) / 1024 ** 2, 1)
+                    break
+    except OSError:
+        pass
+    try:
+        usable = len(os.sched_getaffinity(0))
+    except (AttributeError, OSError):
+        usable = os.cpu_count()
+    return {"cpu_model": model, "nproc": os.cpu_count(), "usable_cpus": usable, "ram_gb": mem_gb}
+
+
+def cpu_baseline_share(args, datagen, seed):
+    """The oracle (both passes over the rows + exact-rational finalize) on a
+    bounded prefix of the same table: all usable host threads (at most 16,
+    the machine's CPU share per GPU) on the first args.cpu_sample_rows rows, and
+    one thread on a sixteenth of them.  Generation is not timed."""
+    import oracle
+    info = host_info()
+    threads = max(1, min(16, info["usable_cpus"] or 1))
+    S = min(args.cpu_sample_rows, args.rows)
+    S1 = max(1, S // 16)
+    is_int = [True] * 8 + [False, True]
+    hostp = datagen.table1_planar_threaded(seed, S, threads)
+    tc0 = time.perf_counter()
+    st = oracle.sufficient_stats(hostp, is_int, threads=threads)
+    ref = oracle.finalize(st, mask=range(1, 10))
+    tc1 = time.perf_counter()
+    one = [c[:S1] for c in hostp]
+    ts0 = time.perf_counter()
+    st1 = oracle.sufficient_stats(one, is_int, threads=1)
+    oracle.finalize(st1, mask=range(1, 10))
+    ts1 = time.perf_counter()
+    del hostp, one
+    return {"value": round(S / (tc1 - tc0), 1), "unit": "rows/s", "cores": threads, "kind": "oracle",
+            "sample": f"first {S} rows of the same table on {threads} threads "
+                      f"(both passes + finalize, {tc1 - tc0:.1f} s); one thread: first {S1} rows "
+                      f"({ts1 - ts0:.1f} s)",
+            "single_core_rows_per_s": round(S1 / (ts1 - ts0), 1), "host": info,
+            "_rows": S, "_ref_cov": ref["cov"]}
+
+
 # ---- share: 2e9 Table-1 rows, int32 x 9 + FP64 planes ------------------------
 
 def run_share(args, L, torch, datagen):
@@ -124,9 +196,11 @@ def run_share(args, L, torch, datagen):
         # pinned host copy of the same rows; the copies through the staging
         # ring are inside the timed region (PCIe-inclusive rate)
         log("copying the rows to pinned host memory")
+        tg = time.perf_counter()
         host = [torch.empty(N, dtype=dt, pin_memory=True) for dt in dts]
         for hp, dp in zip(host, planes):
             hp.copy_(dp)
+        gen_s = time.perf_counter() - tg
         del planes
         torch.cuda.empty_cache()
         bases = [p.data_ptr() for p in host]
@@ -176,23 +250,18 @@ def run_share(args, L, torch, datagen):
     log(f"step {ms_per_step:.2f} ms, {rows_per_s:.3e} rows/s, kernel {roof['achieved']:.0f} GB/s")
     cpu = None
     if not args.no_cpu_baseline:
-        import oracle
-        S = min(args.cpu_sample_rows, N)
-        hostp = datagen.table1_planar(seed, S)
-        is_int = [True] * 8 + [False, True]
-        tc0 = time.perf_counter()
-        st = oracle.sufficient_stats(hostp, is_int)
-        ref = oracle.finalize(st, mask=range(1, 10))
-        tc1 = time.perf_counter()
-        cpu = {"value": round(S / (tc1 - tc0), 1), "unit": "rows/s", "cores": 1, "kind": "oracle",
-               "sample": f"first {S} rows of the same table (both passes + finalize), "
-                         f"{tc1 - tc0:.1f} s on the host"}
+        cpu = cpu_baseline_share(args, datagen, seed)
         if kind == L.STATS_MEM_DEVICE:
+            # the GPU on the same prefix as the all-core oracle run
             L.stats_reset(h)
-            L.stats_accumulate(h, bases, S)
+            L.stats_accumulate(h, bases, cpu.pop("_rows"))
             fs = L.stats_finalize(h, 10)
-            cpu["gpu_cov_rel_err_vs_oracle"] = cov_err(fs["cov"], ref["cov"])
-            log(f"oracle {cpu['value']:.3g} rows/s; cov rel err {cpu['gpu_cov_rel_err_vs_oracle']:.2e}")
+            cpu["gpu_cov_rel_err_vs_oracle"] = cov_err(fs["cov"], cpu.pop("_ref_cov"))
+            log(f"oracle {cpu['value']:.3g} rows/s on {cpu['cores']} threads; "
+                f"cov rel err {cpu['gpu_cov_rel_err_vs_oracle']:.2e}")
+        else:
+            cpu.pop("_rows")
+            cpu.pop("_ref_cov")
     if args.calibrate_copy:
         # a plain copy of known size for scaling the HBM traffic counters
         a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
@@ -201,14 +270,18 @@ def run_share(args, L, torch, datagen):
         torch.cuda.synchronize()
     L.stats_close(h)
     out = base_json(args, rows_per_s, "rows/s", ms_per_step, "f64",
-                    {"workload": "table1_share_2e9_rows_int32x9_fp64_" +
-                     ("pinned_host" if host is not None else "hbm"),
+                    {"workload": ("table1_share_2e9_rows" if N == 2_000_000_000 else f"table1_{N}_rows") +
+                     "_int32x9_fp64_" + ("pinned_host" if host is not None else "hbm"),
                      "rows": N, "p": 10, "chunk_rows": CH, "bytes_per_row": bpr,
                      "step": "reset + accumulate all chunks + finalize (cov, corr, PCA)"})
     out["hbm_gbs_end_to_end"] = round(N * args.steps * bpr / elapsed / 1e9, 1)
     if host is not None:
         out["pcie_copy_gbs"] = round(N * args.steps * bpr / ((cms1 - cms0) / 1e3) / 1e9, 1) if cms1 > cms0 else None
         out["copy_launches"] = c1 - c0
+        peak = pinned_h2d_peak(torch)
+        out["pinned_h2d_peak_gbs"] = round(peak, 1)
+        out["link_frac_of_h2d_peak"] = round(out["hbm_gbs_end_to_end"] / peak, 4)
+        out["host_generation_s_untimed"] = round(gen_s, 1)
     out["roofline"] = roof
     out["cpu_baseline"] = cpu
     return out
@@ -323,16 +396,22 @@ def run_wide(args, L, torch, datagen):
     lam_err = float(np.max(np.abs(res["split"]["fin"]["eigval"] - res["fp64"]["fin"]["eigval"])) /
                     np.max(res["fp64"]["fin"]["eigval"]))
     T = p * (p + 1) // 2
-    flops_split = 9 * 2.0 * N * T
     sp = res["split"]
-    achieved = flops_split / (sp["syrk_ms"] / 1e3) / 1e12
+    # algorithmic work per row: 1028 bytes read; p(p+1) = 2T flops (the upper
+    # triangle of x x^T); the split kernel issues nine BF16 digit products per
+    # pair, 9 x 2T flops, on the matrix cores
+    bytes_row = 4 * 256 + 4
+    launches = max(sp["launches_per_pass"], 1)
     out = base_json(args, N / (sp["accumulate_ms"] / 1e3), "rows/s", sp["accumulate_ms"], "bf16x3",
                     {"workload": f"gauss_fp32_{N}x256_plus_int32_id", "rows": N, "p": p,
-                     "bytes_per_row": 1028, "step": "reset + accumulate (split BF16 matrix cores) + sync"})
-    out["roofline"] = {"bound": "mfma", "achieved": round(achieved, 1), "peak": BF16_PEAK_TFLOPS,
-                       "unit": "TFLOP/s", "frac": round(achieved / BF16_PEAK_TFLOPS, 4), "traffic": None,
-                       "kernel": "k_syrk_split (9 BF16 digit products per pair)",
-                       "algorithmic_flops_per_pass": flops_split}
+                     "bytes_per_row": bytes_row, "step": "reset + accumulate (split BF16 matrix cores) + sync"})
+    out["roofline"] = hbm_roofline("k_syrk_split (split BF16 digits on the matrix cores)", N * bytes_row,
+                                   sp["syrk_ms"], int(round(launches)), N * bytes_row / launches)
+    algo = 2.0 * N * T / (sp["syrk_ms"] / 1e3) / 1e12
+    out["roofline"]["mfma"] = {"algorithmic_tflops": round(algo, 1), "frac_of_bf16_peak": round(algo / BF16_PEAK_TFLOPS, 4),
+                               "issued_digit_product_tflops": round(9 * algo, 1),
+                               "issued_frac_of_bf16_peak": round(9 * algo / BF16_PEAK_TFLOPS, 4),
+                               "algorithmic_flops_per_row": 2 * T}
     out["hbm_gbs"] = round(N * 1028 / (sp["accumulate_ms"] / 1e3) / 1e9, 1)
     out["fp64_path"] = {"accumulate_ms": round(res["fp64"]["accumulate_ms"], 2),
                         "syrk_ms": round(res["fp64"]["syrk_ms"], 2),
@@ -506,16 +585,14 @@ def main():
     ap.add_argument("--p", type=int, default=10, choices=[10, 16], help="c1: columns (16 = 128-byte rows)")
     ap.add_argument("--chunk-rows", type=int, default=1 << 28)
     ap.add_argument("--wave-rows", type=int, default=600_000_000)
-    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 26)
+    ap.add_argument("--cpu-sample-rows", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-staged", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
     args = ap.parse_args()
     args.rows_given = args.rows is not None
     if args.rows is None:
-        # the pinned-host run streams a 2^29-row slice of the share (23.6 GB
-        # of page-locked memory); the HBM-resident run takes the whole share
-        args.rows = (1 << 29) if args.host_staged else 2_000_000_000
+        args.rows = 2_000_000_000
 
     world = int(os.environ.get("WORLD_SIZE", "1"))
     if args.gpus != 1 or world != 1:

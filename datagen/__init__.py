@@ -118,6 +118,26 @@ def table1_planar(seed: int, n: int, row0: int = 0, a0: int | None = None) -> li
     return planes
 
 
+def table1_planar_threaded(seed: int, n: int, threads: int = 16) -> list[np.ndarray]:
+    """table1_planar(seed, n) with the rows split over host threads (the C
+    generator is counter-based, so the bytes do not depend on the split)."""
+    planes = [np.empty(n, dtype=dt) for dt in PLANAR_DTYPES]
+    if n == 0:
+        return planes
+    from concurrent.futures import ThreadPoolExecutor
+    cuts = [n * k // threads for k in range(threads + 1)]
+
+    def fill(k):
+        a, b = cuts[k], cuts[k + 1]
+        if b > a:
+            ptrs = (ctypes.c_void_p * 10)(*[p.ctypes.data + a * p.itemsize for p in planes])
+            host().dg_table1_planar(seed, a, a + 1, b - a, ptrs)
+
+    with ThreadPoolExecutor(threads) as ex:
+        list(ex.map(fill, range(threads)))
+    return planes
+
+
 def groups_aos(seed: int, n: int, row0: int, a0: int) -> np.ndarray:
     """(n, 32) float64: 10 Table-1 columns (identifier a0..) + 22 U{0..100}."""
     out = np.empty((n, 32), dtype=np.float64)

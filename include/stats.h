@@ -64,7 +64,8 @@ enum {
   STATS_E_NOMEM = -4,    /* device or pinned allocation failed */
   STATS_E_INEXACT = -5,  /* an integer column left the exact range */
   STATS_E_PARSE = -6,    /* malformed text input */
-  STATS_E_MISMATCH = -7  /* stats_merge of incompatible handles */
+  STATS_E_MISMATCH = -7, /* stats_merge of incompatible handles */
+  STATS_E_IO = -8        /* a file could not be opened or read */
 };
 
 /* Column storage types. */
@@ -87,7 +88,12 @@ enum {
 };
 
 /* Configuration flags. */
-enum { STATS_CFG_TIMING = 1u /* record per-kernel HIP event timings */ };
+enum {
+  STATS_CFG_TIMING = 1u,   /* record per-kernel HIP event timings */
+  STATS_CFG_PAIRWISE = 2u  /* missing values: NaN entries are absent, statistics per
+                              pair of columns over the rows where both are present
+                              (stats_finalize_pairwise); p <= 16, FP32/FP64 columns */
+};
 
 /* Column c of a row: element of type dtype at byte offset byte_offset inside
  * row r of plane `plane`, i.e. at planes[plane] + r * row_stride[plane] +
@@ -161,6 +167,19 @@ int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t nrows, int
 #define STATS_NOALLOC_SCRATCH_BYTES (8u << 20)
 int stats_accumulate_noalloc(stats_ctx* h, const void* const* planes, int64_t nrows);
 
+/* Adds nrows fixed-width records read from a file: the storage -> host
+ * memory -> GPU path of section "System Overview", on the binary form that
+ * section "Data Representation and Sufficient Statistics" makes canonical.
+ * The handle must have one plane; record r starts at byte
+ * offset + r * row_stride[0] of the file at path.  Chunks of staging_rows
+ * records are read by positioned reads on up to eight host threads into two
+ * page-locked slots; each chunk's read overlaps the copy and reduction of
+ * the previous chunk (same two-slot ring as STATS_MEM_HOST input).  The call
+ * returns once every row has been read (the reduction of the last chunk may
+ * still run).  STATS_E_IO: the file cannot be opened, is shorter than
+ * offset + nrows * row_stride[0] bytes, or a read fails. */
+int stats_accumulate_file(stats_ctx* h, const char* path, int64_t offset, int64_t nrows);
+
 /* Adds the complete lines of a CSV text chunk, parsed on the GPU and fed
  * straight into the same accumulation (the paper's first pipeline streamed
  * CSV in fixed-size chunks: section "Validation and Infrastructure Testing";
@@ -174,6 +193,47 @@ int stats_accumulate_noalloc(stats_ctx* h, const void* const* planes, int64_t nr
  * STATS_E_PARSE with its byte offset in stats_last_error(). */
 int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
                           int32_t is_last, int64_t* bytes_consumed);
+
+/* Converts the complete lines of a CSV text chunk into fixed-width binary
+ * rows on the GPU: the one-time conversion of section "Data Representation
+ * and Sufficient Statistics" (the binary form replaces repeated CSV parsing),
+ * whose output is then checked as in section "Validation and Infrastructure
+ * Testing" (file size, row count, layout, sample records).  The handle only
+ * describes the layout: line k of the chunk becomes row k of the output,
+ * field c written at out_planes[cols[c].plane] + k * row_stride[plane] +
+ * cols[c].byte_offset (device memory) as cols[c].dtype; its statistics are
+ * not touched.  Text rules and chunking as stats_accumulate_text (the same
+ * parser: integer columns exactly, decimal columns correctly rounded to
+ * FP64; *bytes_consumed = bytes of the complete lines).  Column types: I32,
+ * I64 or F64 for integer columns, F64 for decimal columns (else STATS_E_ARG;
+ * FP32 output would round twice).  *rows_out = lines converted; the chunk
+ * may hold at most max_rows lines (else STATS_E_ARG, nothing written).
+ * STATS_E_PARSE: a malformed field, an integer outside int32 for an I32
+ * column or beyond 2^53 for an F64 one; the byte offset of its line is in
+ * stats_last_error() and the output rows are then unspecified.  Returns
+ * after the conversion has finished.  p <= 16. */
+int stats_text_to_binary(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
+                         int32_t is_last, void* const* out_planes, int64_t max_rows,
+                         int64_t* rows_out, int64_t* bytes_consumed);
+
+/* Statistics with missing values (handle opened with STATS_CFG_PAIRWISE):
+ * the extension to incomplete data that section "Limitations and Future
+ * Work" names.  A NaN entry is absent; for every pair of columns (i, j) the
+ * rows where both are present form the pair's sample (pairwise deletion).
+ * stats_accumulate (any memory kind) and stats_merge (two pairwise handles)
+ * work as for complete data; stats_raw, stats_finalize, stats_serialize and
+ * text input return STATS_E_STATE on such a handle.  Outputs, host arrays
+ * (any may be NULL): n_out p x p counts n_ij (n_ii = present entries of
+ * column i); mean_out p means of each column over its own present entries;
+ * cov_out p x p, cov_ij = sum over the pair's rows of (x_i - m_i)(x_j - m_j)
+ * / (n_ij - ddof) with m_i, m_j the means over those same rows (NaN when
+ * n_ij <= ddof); corr_out p x p, corr_ij = that co-moment over the square
+ * root of the two centred sums of squares over the same rows (diagonal 1,
+ * NaN when a column is constant or absent on them).  Such a matrix need not
+ * be positive semi-definite, so no components are formed from it.  FP64
+ * throughout, no exact integer path. */
+int stats_finalize_pairwise(stats_ctx* h, int32_t ddof, int64_t* n_out, double* mean_out,
+                            double* cov_out, double* corr_out);
 
 /* Batched groups: a handle holding ngroups independent sets of the
  * statistics of section "Data Representation and Sufficient Statistics"

@@ -18,6 +18,10 @@ GPU-Accelerated Multivariate Statistics Platform"):
 * ``integer_sums`` -- the exact (n, s, C) of integer-valued columns alone
   (one __int128 pass), for checks at sizes where the full two-pass oracle is
   too slow.
+* ``pairwise_stats`` -- the statistics of columns with missing values (NaN),
+  pair by pair over the rows where both are present (pairwise deletion),
+  from two compensated C passes; ``pairwise_brute_force`` computes the same
+  in exact rational arithmetic for small inputs (its pin).
 * ``brute_force`` -- the same quantities with exact rational arithmetic
   (``fractions.Fraction``) for tiny inputs: the pin for everything above.
 
@@ -85,6 +89,10 @@ def _L() -> ctypes.CDLL:
         lib.oracle_pass2.argtypes = [vp, i32, i64, i64, vp, vp]
         lib.oracle_pass_int.restype = ctypes.c_int
         lib.oracle_pass_int.argtypes = [vp, i32, i64, i64, vp, vp]
+        lib.oracle_pw_pass1.restype = None
+        lib.oracle_pw_pass1.argtypes = [vp, i32, i64, i64, vp, vp, vp]
+        lib.oracle_pw_pass2.restype = None
+        lib.oracle_pw_pass2.argtypes = [vp, i32, i64, i64, vp, vp, vp, vp, vp]
         lib.oracle_parse_csv.restype = i64
         lib.oracle_parse_csv.argtypes = [vp, i64, i32, vp, vp, i64]
         _lib = lib
@@ -375,6 +383,107 @@ def pca(M):
 
 # ---- exact brute force (tiny inputs) -----------------------------------------
 
+def pairwise_brute_force(cols, ddof: int = 1):
+    """Statistics of columns with missing values (NaN), pairwise-complete:
+    for every pair (i, j) the rows where both are present, their count, the
+    two columns' means over those rows and the covariance and correlation
+    from those rows alone (pairwise deletion; the missing-value extension of
+    section "Limitations and Future Work").  Exact rational arithmetic on the
+    stored values, one rounding to FP64 (the correlation's square root at 60
+    digits).  Returns n (p x p), mean (p: each column over its own present
+    rows), cov and corr (p x p; NaN where undefined)."""
+    import mpmath
+    cols = [np.asarray(c, dtype=np.float64) for c in cols]
+    p = len(cols)
+    n = np.zeros((p, p), dtype=np.int64)
+    cov = np.full((p, p), np.nan)
+    corr = np.full((p, p), np.nan)
+    mean = np.full(p, np.nan)
+    present = [~np.isnan(c) for c in cols]
+    for i in range(p):
+        for j in range(i, p):
+            both = present[i] & present[j]
+            m = int(both.sum())
+            n[i, j] = n[j, i] = m
+            if m == 0:
+                continue
+            xi = [Fraction(float(v)) for v in cols[i][both]]
+            xj = [Fraction(float(v)) for v in cols[j][both]]
+            mi, mj = sum(xi, Fraction(0)) / m, sum(xj, Fraction(0)) / m
+            if i == j:
+                mean[i] = float(mi)
+            cij = sum(((a - mi) * (b - mj) for a, b in zip(xi, xj)), Fraction(0))
+            cii = sum(((a - mi) ** 2 for a in xi), Fraction(0))
+            cjj = sum(((b - mj) ** 2 for b in xj), Fraction(0))
+            if m > ddof:
+                cov[i, j] = cov[j, i] = float(cij / (m - ddof))
+            if cii > 0 and cjj > 0:
+                if i == j:
+                    r = 1.0
+                else:
+                    with mpmath.workdps(60):
+                        r = float(mpmath.mpf(cij.numerator) / cij.denominator / sqrt_fraction(cii * cjj))
+                corr[i, j] = corr[j, i] = r
+    return {"n": n, "mean": mean, "cov": cov, "corr": corr}
+
+
+def pairwise_stats(cols, ddof: int = 1):
+    """pairwise_brute_force's results by two compensated passes in C (the
+    pair's count and sums over the rows where both columns are present, then
+    the centred products about its rounded means), finished in exact rational
+    arithmetic: usable on many rows."""
+    import mpmath
+    cols = [np.ascontiguousarray(np.asarray(c)) for c in cols]
+    p = len(cols)
+    T = p * (p + 1) // 2
+    m = len(cols[0]) if p else 0
+    arr, keep = _cols_struct([(c, False) for c in cols])
+    cnt = np.zeros(T, dtype=np.int64)
+    si = np.zeros(2 * T)
+    sj = np.zeros(2 * T)
+    _L().oracle_pw_pass1(arr, p, 0, m, cnt.ctypes.data, si.ctypes.data, sj.ctypes.data)
+    ex_i = [Fraction(float(si[2 * t])) + Fraction(float(si[2 * t + 1])) for t in range(T)]
+    ex_j = [Fraction(float(sj[2 * t])) + Fraction(float(sj[2 * t + 1])) for t in range(T)]
+    mi = [ex_i[t] / int(cnt[t]) if cnt[t] else Fraction(0) for t in range(T)]
+    mj = [ex_j[t] / int(cnt[t]) if cnt[t] else Fraction(0) for t in range(T)]
+    a = np.array([float(v) for v in mi])
+    b = np.array([float(v) for v in mj])
+    cij = np.zeros(2 * T)
+    cii = np.zeros(2 * T)
+    cjj = np.zeros(2 * T)
+    _L().oracle_pw_pass2(arr, p, 0, m, a.ctypes.data, b.ctypes.data, cij.ctypes.data, cii.ctypes.data,
+                         cjj.ctypes.data)
+    del keep
+    n = np.zeros((p, p), dtype=np.int64)
+    cov = np.full((p, p), np.nan)
+    corr = np.full((p, p), np.nan)
+    mean = np.full(p, np.nan)
+    for i in range(p):
+        for j in range(i, p):
+            t = tri_index(p, i, j)
+            k = int(cnt[t])
+            n[i, j] = n[j, i] = k
+            if k == 0:
+                continue
+            if i == j:
+                mean[i] = float(mi[t])
+            # sum (x - m)(y - m') = sum (x - a)(y - b) - k (m - a)(m' - b)
+            da, db = mi[t] - Fraction(a[t]), mj[t] - Fraction(b[t])
+            c = Fraction(float(cij[2 * t])) + Fraction(float(cij[2 * t + 1])) - k * da * db
+            u = Fraction(float(cii[2 * t])) + Fraction(float(cii[2 * t + 1])) - k * da * da
+            w = Fraction(float(cjj[2 * t])) + Fraction(float(cjj[2 * t + 1])) - k * db * db
+            if k > ddof:
+                cov[i, j] = cov[j, i] = float(c / (k - ddof))
+            if u > 0 and w > 0:
+                if i == j:
+                    r = 1.0
+                else:
+                    with mpmath.workdps(60):
+                        r = float(mpmath.mpf(c.numerator) / c.denominator / sqrt_fraction(u * w))
+                corr[i, j] = corr[j, i] = r
+    return {"n": n, "mean": mean, "cov": cov, "corr": corr}
+
+
 def brute_force(rows, ddof: int = 1):
     """Exact rational n, s, C, M2 and cov of a small list of rows.
 
@@ -423,5 +532,5 @@ def sqrt_fraction(x: Fraction, digits: int = 60):
 
 
 __all__ = ["OracleStats", "sufficient_stats", "sufficient_stats_stream", "integer_sums", "finalize",
-           "pca", "eig_sym",
+           "pca", "eig_sym", "pairwise_stats", "pairwise_brute_force",
            "brute_force", "parse_csv", "tri_index", "columns_of", "build"]

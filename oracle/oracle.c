@@ -202,6 +202,75 @@ void oracle_pass2(const oc_col* cols, int32_t p, int64_t r0, int64_t r1, const d
   free(acc); free(dh); free(dl);
 }
 
+/* Missing values (NaN) and pairwise deletion: pass 1 over rows [r0, r1) gives,
+ * for every pair t = (i <= j), the number of rows where both columns are
+ * present and the compensated (hi, lo) sums of x_i and of x_j over those
+ * rows. */
+void oracle_pw_pass1(const oc_col* cols, int32_t p, int64_t r0, int64_t r1, int64_t* n, double* si,
+                     double* sj) {
+  const int64_t T = (int64_t)p * (p + 1) / 2;
+  comp* a = (comp*)calloc((size_t)T, sizeof(comp));
+  comp* b = (comp*)calloc((size_t)T, sizeof(comp));
+  double* x = (double*)calloc((size_t)p, sizeof(double));
+  for (int64_t r = r0; r < r1; ++r) {
+    for (int i = 0; i < p; ++i) x[i] = get_f64(&cols[i], r);
+    for (int i = 0; i < p; ++i) {
+      if (isnan(x[i])) continue;
+      for (int j = i; j < p; ++j) {
+        if (isnan(x[j])) continue;
+        const int64_t t = tri(p, i, j);
+        n[t] += 1;
+        comp_add(&a[t], x[i]);
+        comp_add(&b[t], x[j]);
+      }
+    }
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    si[2 * t] = a[t].hi;
+    si[2 * t + 1] = a[t].lo;
+    sj[2 * t] = b[t].hi;
+    sj[2 * t + 1] = b[t].lo;
+  }
+  free(a); free(b); free(x);
+}
+
+/* Pass 2: over the rows where both columns of pair t are present, the
+ * compensated sums of (x_i - ma_t)(x_j - mb_t), (x_i - ma_t)^2 and
+ * (x_j - mb_t)^2 (each difference kept exactly as a TwoSum pair). */
+void oracle_pw_pass2(const oc_col* cols, int32_t p, int64_t r0, int64_t r1, const double* ma,
+                     const double* mb, double* cij, double* cii, double* cjj) {
+  const int64_t T = (int64_t)p * (p + 1) / 2;
+  comp* c = (comp*)calloc((size_t)T, sizeof(comp));
+  comp* u = (comp*)calloc((size_t)T, sizeof(comp));
+  comp* w = (comp*)calloc((size_t)T, sizeof(comp));
+  double* x = (double*)calloc((size_t)p, sizeof(double));
+  for (int64_t r = r0; r < r1; ++r) {
+    for (int i = 0; i < p; ++i) x[i] = get_f64(&cols[i], r);
+    for (int i = 0; i < p; ++i) {
+      if (isnan(x[i])) continue;
+      for (int j = i; j < p; ++j) {
+        if (isnan(x[j])) continue;
+        const int64_t t = tri(p, i, j);
+        double ah, al, bh, bl;
+        two_sum(x[i], -ma[t], &ah, &al);
+        two_sum(x[j], -mb[t], &bh, &bl);
+        comp_add_prod(&c[t], ah, al, bh, bl);
+        comp_add_prod(&u[t], ah, al, ah, al);
+        comp_add_prod(&w[t], bh, bl, bh, bl);
+      }
+    }
+  }
+  for (int64_t t = 0; t < T; ++t) {
+    cij[2 * t] = c[t].hi;
+    cij[2 * t + 1] = c[t].lo;
+    cii[2 * t] = u[t].hi;
+    cii[2 * t + 1] = u[t].lo;
+    cjj[2 * t] = w[t].hi;
+    cjj[2 * t + 1] = w[t].lo;
+  }
+  free(c); free(u); free(w); free(x);
+}
+
 /* CSV parse: complete lines of p comma-separated fields.  Field j is read
  * with strtoll when is_int[j] (stored as double, exact below 2^53) and with
  * strtod otherwise.  Writes up to max_rows rows (row-major, p doubles each);

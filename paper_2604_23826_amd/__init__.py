@@ -35,12 +35,13 @@ STATS_MAX_P = 1024
 STATS_MAX_PLANES = 32
 STATS_MASK_WORDS = STATS_MAX_P // 64
 STATS_OK, STATS_E_ARG, STATS_E_STATE, STATS_E_HIP, STATS_E_NOMEM = 0, -1, -2, -3, -4
-STATS_E_INEXACT, STATS_E_PARSE, STATS_E_MISMATCH = -5, -6, -7
+STATS_E_INEXACT, STATS_E_PARSE, STATS_E_MISMATCH, STATS_E_IO = -5, -6, -7, -8
 STATS_I32, STATS_I64, STATS_F32, STATS_F64 = 1, 2, 3, 4
 STATS_COL_INTEGER, STATS_COL_IDENTIFIER = 1, 2
 STATS_MEM_DEVICE, STATS_MEM_HOST_PINNED, STATS_MEM_HOST = 0, 1, 2
 STATS_PREC_FP64, STATS_PREC_SPLIT_BF16, STATS_PREC_AUTO = 0, 1, 2
 STATS_CFG_TIMING = 1
+STATS_CFG_PAIRWISE = 2
 STATS_NOALLOC_SCRATCH_BYTES = 8 << 20
 (STATS_K_ACCUM, STATS_K_MERGE, STATS_K_FINALIZE, STATS_K_SYRK, STATS_K_SEGMENTED,
  STATS_K_TEXT, STATS_K_COPY, STATS_K_COUNT) = range(8)
@@ -78,6 +79,9 @@ _sig = {
     "stats_open_groups": [ctypes.POINTER(Config), _i32, ctypes.POINTER(_vp)],
     "stats_accumulate": [_vp, _vp, _i64, _i32],
     "stats_accumulate_noalloc": [_vp, _vp, _i64],
+    "stats_accumulate_file": [_vp, ctypes.c_char_p, _i64, _i64],
+    "stats_finalize_pairwise": [_vp, _i32, _vp, _vp, _vp, _vp],
+    "stats_text_to_binary": [_vp, _vp, _i64, _i32, _i32, _vp, _i64, ctypes.POINTER(_i64), ctypes.POINTER(_i64)],
     "stats_accumulate_text": [_vp, _vp, _i64, _i32, _i32, ctypes.POINTER(_i64)],
     "stats_accumulate_segmented": [_vp, _vp, _vp, _i32],
     "stats_merge": [_vp, _vp],
@@ -132,7 +136,8 @@ def _ptr(x) -> int:
 
 
 def make_config(columns, row_strides, device: int = 0, stream=None, precision: int = STATS_PREC_AUTO,
-                block_rows: int = 0, staging_rows: int = 0, timing: bool = False) -> Config:
+                block_rows: int = 0, staging_rows: int = 0, timing: bool = False,
+                pairwise: bool = False) -> Config:
     """columns: list of (dtype_code, plane, byte_offset, flags)."""
     cols = (Column * len(columns))(*[Column(*c) for c in columns])
     cfg = Config()
@@ -147,7 +152,7 @@ def make_config(columns, row_strides, device: int = 0, stream=None, precision: i
     cfg.stream = stream
     cfg.staging_rows = staging_rows
     cfg.block_rows = block_rows
-    cfg.flags = STATS_CFG_TIMING if timing else 0
+    cfg.flags = (STATS_CFG_TIMING if timing else 0) | (STATS_CFG_PAIRWISE if pairwise else 0)
     return cfg
 
 
@@ -163,6 +168,26 @@ def stats_open_groups(cfg: Config, ngroups: int) -> int:
     return h.value
 
 
+# Device tensors handed to a call that returns before its kernels have read
+# them: the handle's work is ordered on its own stream, which torch's caching
+# allocator does not know of, so a temporary freed on return could be handed
+# out again (and overwritten) while still being read.  The binding keeps them
+# referenced until the next call that waits for the handle's stream (sync,
+# raw, finalize, serialize, close) -- the lifetime the C interface asks of
+# its callers.
+_held: dict = {}
+
+
+def _hold(h: int, objs) -> None:
+    keep = [o for o in objs if hasattr(o, "data_ptr")]
+    if keep:
+        _held.setdefault(h, []).extend(keep)
+
+
+def _release(h: int) -> None:
+    _held.pop(h, None)
+
+
 def _planes(planes):
     arr = (_vp * STATS_MAX_PLANES)()
     for k, p in enumerate(planes):
@@ -172,11 +197,40 @@ def _planes(planes):
 
 def stats_accumulate(h: int, planes, nrows: int, mem_kind: int = STATS_MEM_DEVICE) -> None:
     _check(_lib.stats_accumulate(h, _planes(planes), nrows, mem_kind))
+    _hold(h, planes)
 
 
 def stats_accumulate_noalloc(h: int, planes, nrows: int) -> None:
     """Device input, p <= 16, no allocation in the call (see stats.h)."""
     _check(_lib.stats_accumulate_noalloc(h, _planes(planes), nrows))
+    _hold(h, planes)
+
+
+def stats_accumulate_file(h: int, path: str, offset: int, nrows: int) -> None:
+    """Fixed-width records of a file (one-plane handle; see stats.h)."""
+    _check(_lib.stats_accumulate_file(h, os.fsencode(path), offset, nrows))
+
+
+def stats_finalize_pairwise(h: int, p: int, ddof: int = 1) -> dict:
+    """n, mean, cov, corr of a pairwise (missing-value) handle (see stats.h)."""
+    n = np.zeros((p, p), dtype=np.int64)
+    mean = np.zeros(p)
+    cov = np.zeros((p, p))
+    corr = np.zeros((p, p))
+    _check(_lib.stats_finalize_pairwise(h, ddof, n.ctypes.data, mean.ctypes.data, cov.ctypes.data,
+                                        corr.ctypes.data))
+    _release(h)
+    return {"n": n, "mean": mean, "cov": cov, "corr": corr}
+
+
+def stats_text_to_binary(h: int, buf, nbytes: int, out_planes, max_rows: int,
+                         mem_kind: int = STATS_MEM_DEVICE, is_last: bool = False):
+    """(rows written, bytes consumed) of a CSV chunk converted on the GPU into
+    the handle's binary layout (see stats.h)."""
+    rows, used = _i64(0), _i64(0)
+    _check(_lib.stats_text_to_binary(h, _ptr(buf), nbytes, mem_kind, 1 if is_last else 0,
+                                     _planes(out_planes), max_rows, ctypes.byref(rows), ctypes.byref(used)))
+    return rows.value, used.value
 
 
 def stats_accumulate_text(h: int, buf, nbytes: int, mem_kind: int = STATS_MEM_DEVICE,
@@ -184,6 +238,7 @@ def stats_accumulate_text(h: int, buf, nbytes: int, mem_kind: int = STATS_MEM_DE
     used = _i64(0)
     _check(_lib.stats_accumulate_text(h, _ptr(buf), nbytes, mem_kind, 1 if is_last else 0,
                                       ctypes.byref(used)))
+    _hold(h, [buf])
     return used.value
 
 
@@ -191,6 +246,7 @@ def stats_accumulate_segmented(h: int, planes, row_offsets: np.ndarray,
                                mem_kind: int = STATS_MEM_DEVICE) -> None:
     off = np.ascontiguousarray(row_offsets, dtype=np.int64)
     _check(_lib.stats_accumulate_segmented(h, _planes(planes), off.ctypes.data, mem_kind))
+    _hold(h, planes)
 
 
 def stats_merge(dst: int, src: int) -> None:
@@ -199,6 +255,7 @@ def stats_merge(dst: int, src: int) -> None:
 
 def stats_sync(h: int) -> None:
     _check(_lib.stats_sync(h))
+    _release(h)
 
 
 def stats_reset(h: int) -> None:
@@ -227,6 +284,7 @@ def stats_raw(h: int, p: int) -> dict:
     o = _raw_outputs(p)
     _check(_lib.stats_raw(h, ctypes.byref(o["n"]), o["s_int"], o["s_f64"].ctypes.data, o["C_int"],
                           o["C_f64"].ctypes.data, o["exact"].ctypes.data))
+    _release(h)
     return _raw_result(o, p)
 
 
@@ -234,6 +292,7 @@ def stats_group_raw(h: int, g: int, p: int) -> dict:
     o = _raw_outputs(p)
     _check(_lib.stats_group_raw(h, g, ctypes.byref(o["n"]), o["s_int"], o["s_f64"].ctypes.data,
                                 o["C_int"], o["C_f64"].ctypes.data, o["exact"].ctypes.data))
+    _release(h)
     return _raw_result(o, p)
 
 
@@ -262,6 +321,7 @@ def stats_finalize(h: int, p: int, mask=None, ddof: int = 1, pca_on: int = 0,
     _check(_lib.stats_finalize(h, ctypes.byref(o), ctypes.byref(pq),
                                *(flat[k].ctypes.data for k in ("mean", "cov", "corr", "eigval",
                                                                 "eigvec", "var_pct", "cum_pct"))))
+    _release(h)
     qq = pq.value
     return {k: (v[:qq * qq].reshape(qq, qq) if k in ("cov", "corr", "eigvec") else v[:qq])
             for k, v in flat.items()}
@@ -276,6 +336,7 @@ def stats_finalize_groups(h: int, ngroups: int, p: int, mask=None, ddof: int = 1
     pq = _i32(0)
     _check(_lib.stats_finalize_groups(h, ctypes.byref(o), ctypes.byref(pq), n.ctypes.data,
                                       mean.ctypes.data, cov.ctypes.data))
+    _release(h)
     qq = pq.value
     return {"n": n, "mean": mean[:ngroups * qq].reshape(ngroups, qq),
             "cov": cov[:ngroups * qq * qq].reshape(ngroups, qq, qq)}
@@ -286,6 +347,7 @@ def stats_serialize(h: int) -> bytes:
     _check(_lib.stats_serialize(h, None, ctypes.byref(n)))
     buf = ctypes.create_string_buffer(n.value)
     _check(_lib.stats_serialize(h, buf, ctypes.byref(n)))
+    _release(h)
     return buf.raw[:n.value]
 
 
@@ -315,6 +377,7 @@ def stats_read_probe(bufs, nbytes, stream=None) -> float:
 
 def stats_close(h: int) -> None:
     _lib.stats_close(h)
+    _release(h)
 
 
 def library_path() -> str:

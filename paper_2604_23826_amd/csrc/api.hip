@@ -3,6 +3,11 @@
 // accum.hip / merge.hip / finalize.hip (and the wide, segmented and text
 // kernels); this file only moves bytes and sequences work.
 #include <algorithm>
+#include <cerrno>
+#include <thread>
+
+#include <fcntl.h>
+#include <unistd.h>
 #include <cstdio>
 #include <cstring>
 #include <new>
@@ -179,16 +184,32 @@ static int validate_cfg(const stats_config* cfg) {
     return fail(STATS_E_ARG, "block_rows must be 0 or a positive multiple of 1024");
   if (cfg->block_rows > ((int64_t)1 << 24)) return fail(STATS_E_ARG, "block_rows too large");
   if (cfg->staging_rows < 0) return fail(STATS_E_ARG, "staging_rows must be >= 0");
+  if (cfg->flags & ~(uint32_t)(STATS_CFG_TIMING | STATS_CFG_PAIRWISE)) return fail(STATS_E_ARG, "unknown flags");
+  if (cfg->flags & STATS_CFG_PAIRWISE) {
+    if (cfg->p > 16) return fail(STATS_E_ARG, "pairwise (missing-value) statistics support p <= 16");
+    for (int c = 0; c < cfg->p; ++c)
+      if (cfg->cols[c].dtype != STATS_F32 && cfg->cols[c].dtype != STATS_F64)
+        return fail(STATS_E_ARG, "pairwise statistics need FP32 or FP64 columns (NaN = missing)");
+  }
   return STATS_OK;
 }
 
 namespace st {
+
+// Words of one handle state: the complete-data layout, or the per-pair
+// statistics of a pairwise (missing-value) handle.
+int64_t state_words(const stats_ctx* h) {
+  if (h->flags & STATS_CFG_PAIRWISE) return pairwise_state_words(h->p);
+  return Layout::make(h->p).words;
+}
 
 int open_handle(const stats_config* cfg, int ngroups, stats_ctx** out) {
   if (!out) return fail(STATS_E_ARG, "out is NULL");
   *out = nullptr;
   int rc = validate_cfg(cfg);
   if (rc) return rc;
+  if (ngroups > 0 && (cfg->flags & STATS_CFG_PAIRWISE))
+    return fail(STATS_E_ARG, "pairwise statistics are not available for groups handles");
   int ndev = 0;
   if (hipGetDeviceCount(&ndev) != hipSuccess || ndev <= 0)
     return fail(STATS_E_HIP, "no HIP device available");
@@ -220,12 +241,12 @@ int open_handle(const stats_config* cfg, int ngroups, stats_ctx** out) {
     }
     h->own_stream = true;
   }
-  const Layout L = Layout::make(h->p);
+  const int64_t words = state_words(h);
   const int64_t nstates = ngroups > 0 ? ngroups : 1;
   size_t cap;
   for (int k = 0; k < 2; ++k) {
     cap = 0;
-    rc = ensure_dev(h, (void**)&h->state[k], &cap, (size_t)(L.words * 8 * nstates));
+    rc = ensure_dev(h, (void**)&h->state[k], &cap, (size_t)(words * 8 * nstates));
     if (rc) {
       stats_close(h);
       return rc;
@@ -242,7 +263,7 @@ int open_handle(const stats_config* cfg, int ngroups, stats_ctx** out) {
     return rc;
   }
   hipError_t e = hipMemcpyAsync(h->intf_dev, h->intf.data(), (size_t)h->p, hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess) e = hipMemsetAsync(h->state[0], 0, (size_t)(L.words * 8 * nstates), h->stream);
+  if (e == hipSuccess) e = hipMemsetAsync(h->state[0], 0, (size_t)(words * 8 * nstates), h->stream);
   if (e == hipSuccess) e = clear_status(h);
   if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
   if (e != hipSuccess) {
@@ -277,7 +298,8 @@ extern "C" void stats_close(stats_ctx* h) {
   collect_timings(h);
   void* bufs[] = {h->state[0], h->state[1], h->intf_dev, h->status_dev, h->rec,
                   h->fin_out, h->fin_scratch, h->sel_dev, h->raw_out, h->stage_dev[0],
-                  h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev, h->seg_part};
+                  h->stage_dev[1], h->aux_dev, h->aux2_dev, h->aux3_dev, h->seg_part,
+                  h->conv_dev};
   for (void* b : bufs)
     if (b) (void)hipFree(b);
   for (int k = 0; k < 2; ++k) {
@@ -454,7 +476,6 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
   if (p >= 11 && aos_rows_layout(h, planes, 128)) return accumulate_aos_rows(h, planes, nrows, R, 128);
   const AccumLaunch a = accum_launch_of(h, planes);
   const int64_t W = rec_words(p);
-  const Layout L = Layout::make(p);
   // at most 2^28 rows (and 16384 blocks) per launch: plane offsets stay 32-bit
   const int64_t max_rows = std::max<int64_t>(R, std::min<int64_t>(16384 * R, ((int64_t)1 << 28) / R * R));
   int64_t done = 0;
@@ -491,6 +512,7 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
 }
 
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
+  if (h->flags & STATS_CFG_PAIRWISE) return accumulate_pairwise(h, planes, nrows);
   if (h->p <= 16) return accumulate_device_small(h, planes, nrows);
   if (h->p <= 32 && h->precision != STATS_PREC_SPLIT_BF16 && aos_rows_layout(h, planes, 256))
     return accumulate_aos_rows(h, planes, nrows, h->block_rows ? h->block_rows : auto_block_rows(nrows), 256);
@@ -500,7 +522,43 @@ int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
 // Host input: chunks of staging_rows rows go through two device slots; the
 // copy of chunk k+1 (copy stream) overlaps the reduction of chunk k.
 // Pageable input is first copied into two pinned host slots by the CPU.
+// Fills `bytes` bytes at dst from the file at byte offset off with positioned
+// reads split over up to kReaders host threads.  false on a read error or end
+// of file.
+static constexpr int kReaders = 8;
+static bool read_file_range(int fd, char* dst, size_t bytes, int64_t off) {
+  const size_t piece = std::max<size_t>((size_t)1 << 22, (bytes + kReaders - 1) / kReaders);
+  const int n = (int)std::min<size_t>(kReaders, (bytes + piece - 1) / piece);
+  std::vector<char> ok(n, 0);
+  auto work = [&](int k) {
+    size_t a = (size_t)k * piece, b = std::min(bytes, a + piece);
+    while (a < b) {
+      const ssize_t r = pread(fd, dst + a, b - a, (off_t)(off + (int64_t)a));
+      if (r <= 0) {
+        if (r < 0 && errno == EINTR) continue;
+        return;
+      }
+      a += (size_t)r;
+    }
+    ok[k] = 1;
+  };
+  std::vector<std::thread> th;
+  for (int k = 1; k < n; ++k) th.emplace_back(work, k);
+  if (n > 0) work(0);
+  for (auto& t : th) t.join();
+  for (int k = 0; k < n; ++k)
+    if (!ok[k]) return false;
+  return true;
+}
+
 int accumulate_host(stats_ctx* h, const void* const* planes, int64_t nrows, bool pinned) {
+  return accumulate_host_src(h, planes, -1, 0, nrows, pinned);
+}
+
+// Host input from memory planes (fd < 0) or from one file of row-major
+// records (fd >= 0, one plane, record r at byte file_off + r * row_stride[0]).
+int accumulate_host_src(stats_ctx* h, const void* const* planes, int fd, int64_t file_off, int64_t nrows,
+                        bool pinned) {
   const int np = h->n_planes;
   const int64_t S = std::min<int64_t>(h->staging_rows, std::max<int64_t>(nrows, 1));
   if (!h->copy_stream) {
@@ -544,14 +602,21 @@ int accumulate_host(stats_ctx* h, const void* const* planes, int64_t nrows, bool
     hipError_t e = hipStreamWaitEvent(h->copy_stream, h->ev_free[k], 0);
     const void* dplanes[STATS_MAX_PLANES];
     for (int q = 0; q < np && e == hipSuccess; ++q) {
-      const char* src = (const char*)planes[q] + done * h->row_stride[q];
       const size_t bytes = (size_t)(rows * h->row_stride[q]);
       char* dst = (char*)h->stage_dev[k] + plane_off[q];
+      const char* src = fd >= 0 ? nullptr : (const char*)planes[q] + done * h->row_stride[q];
       if (!pinned) {
         e = hipEventSynchronize(h->ev_copy[k]);  // previous DMA out of the host slot done
         if (e != hipSuccess) break;
         char* hs = (char*)h->stage_host[k] + plane_off[q];
-        memcpy(hs, src, bytes);
+        if (fd >= 0) {
+          // the read of this chunk overlaps the copy and reduction of the last
+          if (!read_file_range(fd, hs, bytes, file_off + done * h->row_stride[q]))
+            return fail(STATS_E_IO, "reading rows " + std::to_string(done) + " .. " +
+                                        std::to_string(done + rows) + " of the file failed");
+        } else {
+          memcpy(hs, src, bytes);
+        }
         src = hs;
       }
       Timer t;
@@ -610,12 +675,36 @@ extern "C" int stats_accumulate(stats_ctx* h, const void* const* planes, int64_t
   }
 }
 
+extern "C" int stats_accumulate_file(stats_ctx* h, const char* path, int64_t offset, int64_t nrows) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_accumulate_segmented");
+  if (!path) return fail(STATS_E_ARG, "path is NULL");
+  if (h->n_planes != 1) return fail(STATS_E_ARG, "file input needs a handle with one plane of records");
+  if (nrows < 0 || offset < 0) return fail(STATS_E_ARG, "nrows or offset < 0");
+  if (nrows == 0) return STATS_OK;
+  const int fd = open(path, O_RDONLY | O_CLOEXEC);
+  if (fd < 0) return fail(STATS_E_IO, std::string("cannot open ") + path + ": " + strerror(errno));
+  const off_t end = lseek(fd, 0, SEEK_END);
+  if (end < 0 || (int64_t)end < offset + nrows * h->row_stride[0]) {
+    close(fd);
+    return fail(STATS_E_IO, std::string(path) + " holds fewer than the requested rows");
+  }
+  int rc;
+  {
+    DeviceGuard g(h->device);
+    rc = g.ok ? accumulate_host_src(h, nullptr, fd, offset, nrows, false)
+              : fail(STATS_E_HIP, "hipSetDevice failed");
+  }
+  close(fd);
+  return rc;
+}
+
 extern "C" int stats_reset(stats_ctx* h) {
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   DeviceGuard g(h->device);
-  const Layout L = Layout::make(h->p);
-  const size_t bytes = (size_t)L.words * 8 * (size_t)(h->ngroups > 0 ? h->ngroups : 1);
+  const size_t bytes = (size_t)state_words(h) * 8 * (size_t)(h->ngroups > 0 ? h->ngroups : 1);
   hipError_t e = hipMemsetAsync(h->state[h->cur], 0, bytes, h->stream);
   if (e == hipSuccess) e = clear_status(h);
   if (e != hipSuccess) return hip_fail(h, e, "stats_reset");
@@ -641,22 +730,25 @@ extern "C" int stats_merge(stats_ctx* dst, const stats_ctx* src) {
   if (dst->p != src->p) return fail(STATS_E_MISMATCH, "different column counts");
   for (int c = 0; c < dst->p; ++c)
     if (dst->intf[c] != src->intf[c]) return fail(STATS_E_MISMATCH, "different column kinds");
+  const bool pairwise = (dst->flags & STATS_CFG_PAIRWISE) != 0;
+  if (pairwise != ((src->flags & STATS_CFG_PAIRWISE) != 0))
+    return fail(STATS_E_MISMATCH, "pairwise and complete-data handles");
   stats_ctx* s = const_cast<stats_ctx*>(src);
   DeviceGuard g(dst->device);
-  const Layout L = Layout::make(dst->p);
-  const size_t bytes = (size_t)L.words * 8;
+  const int64_t words = state_words(dst);
+  const size_t bytes = (size_t)words * 8;
   const uint64_t* src_state = s->state[s->cur];
   const DevStatus* src_status = s->status_dev;
   hipError_t e;
   if (s->device != dst->device) {
     // bring the source state and status word over through the host
-    std::vector<uint64_t> tmp(L.words + sizeof(DevStatus) / 8);
+    std::vector<uint64_t> tmp(words + sizeof(DevStatus) / 8);
     {
       DeviceGuard gs(s->device);
       e = hipStreamSynchronize(s->stream);
       if (e == hipSuccess) e = hipMemcpy(tmp.data(), src_state, bytes, hipMemcpyDeviceToHost);
       if (e == hipSuccess)
-        e = hipMemcpy(tmp.data() + L.words, s->status_dev, sizeof(DevStatus), hipMemcpyDeviceToHost);
+        e = hipMemcpy(tmp.data() + words, s->status_dev, sizeof(DevStatus), hipMemcpyDeviceToHost);
       if (e != hipSuccess) return hip_fail(s, e, "reading source state");
     }
     int rc = ensure_dev(dst, &dst->aux_dev, &dst->aux_cap, bytes + sizeof(DevStatus));
@@ -675,8 +767,11 @@ extern "C" int stats_merge(stats_ctx* dst, const stats_ctx* src) {
     if (e == hipSuccess) e = hipEventDestroy(ev);
     if (e != hipSuccess) return hip_fail(dst, e, "ordering src before dst");
   }
-  launch_merge_states(dst->state[dst->cur], src_state, dst->state[dst->cur ^ 1], dst->p,
-                      dst->intf_dev, dst->stream);
+  if (pairwise)
+    launch_pairwise_merge_states(dst->state[dst->cur], src_state, dst->state[dst->cur ^ 1], dst->p, dst->stream);
+  else
+    launch_merge_states(dst->state[dst->cur], src_state, dst->state[dst->cur ^ 1], dst->p,
+                        dst->intf_dev, dst->stream);
   // a deferred error of the source (exactness guard, parse) now holds for dst
   launch_status_or(dst->status_dev, src_status, dst->stream);
   e = hipGetLastError();
@@ -770,6 +865,7 @@ extern "C" int stats_raw(stats_ctx* h, int64_t* n, stats_i128* s_int, double* s_
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_group_raw");
+  if (h->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handle: use stats_finalize_pairwise");
   DeviceGuard g(h->device);
   int rc = sync_handle(h);
   if (rc) return rc;
@@ -782,6 +878,7 @@ extern "C" int stats_finalize(stats_ctx* h, const stats_finalize_opts* opts, int
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_finalize_groups");
+  if (h->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handle: use stats_finalize_pairwise");
   stats_finalize_opts def;
   memset(&def, 0, sizeof def);
   def.ddof = 1;
@@ -858,6 +955,7 @@ extern "C" int stats_serialize(stats_ctx* h, void* buf, size_t* len) {
   if (!h || !len) return fail(STATS_E_ARG, "NULL argument");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   if (h->ngroups) return fail(STATS_E_STATE, "groups handles are not serialized");
+  if (h->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handle: use stats_finalize_pairwise");
   const Layout L = Layout::make(h->p);
   const size_t need = 8 + 8 + (size_t)h->p * 8 + (size_t)L.words * 8;
   if (!buf) {
@@ -891,6 +989,7 @@ extern "C" int stats_deserialize(const void* buf, size_t len, const stats_config
   int64_t p;
   memcpy(&p, (const char*)buf + 8, 8);
   if (p != cfg->p) return fail(STATS_E_MISMATCH, "checkpoint has a different column count");
+  if (cfg->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handles are not serialized");
   const Layout L = Layout::make((int)p);
   if (len != 16 + 8 * (size_t)p + (size_t)L.words * 8) return fail(STATS_E_ARG, "checkpoint size mismatch");
   stats_ctx* h = nullptr;

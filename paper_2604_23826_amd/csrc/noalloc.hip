@@ -49,6 +49,7 @@ extern "C" int stats_accumulate_noalloc(stats_ctx* h, const void* const* planes,
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   if (h->ngroups) return fail(STATS_E_STATE, "groups handle: use stats_accumulate_segmented");
+  if (h->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handle: use stats_accumulate");
   if (h->p > 16)
     return fail(STATS_E_ARG, "stats_accumulate_noalloc: p = " + std::to_string(h->p) +
                                  " exceeds 16 (its fixed scratch serves the narrow kernels only)");

@@ -46,6 +46,8 @@ struct stats_ctx {
   size_t aux2_cap = 0;
   void* aux3_dev = nullptr;
   size_t aux3_cap = 0;
+  void* conv_dev = nullptr;  // text -> binary conversion: line counts, status
+  size_t conv_cap = 0;
 
   // host staging ring (two slots)
   void* stage_dev[2] = {nullptr, nullptr};
@@ -88,6 +90,12 @@ int sync_handle(stats_ctx* h);
 void collect_timings(stats_ctx* h);
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows);
 int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrows);
+int accumulate_host_src(stats_ctx* h, const void* const* planes, int fd, int64_t file_off, int64_t nrows,
+                        bool pinned);
+int pairwise_state_words(int p);
+int64_t state_words(const stats_ctx* h);
+int accumulate_pairwise(stats_ctx* h, const void* const* planes, int64_t nrows);
+void launch_pairwise_merge_states(const uint64_t* a, const uint64_t* b, uint64_t* out, int p, hipStream_t s);
 AccumLaunch accum_launch_of(const stats_ctx* h, const void* const* planes);
 int64_t block_rows_for(const stats_ctx* h, int64_t nrows);
 int raw_of_state(stats_ctx* h, const uint64_t* state_dev, int64_t* n, stats_i128* s_int,

@@ -419,22 +419,11 @@ __device__ inline int parse_line(const Args& a, Cur& C, int L, uint64_t* row, in
   return f;
 }
 
-template <int P>
-__global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
-  __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
-  __shared__ uint64_t s_row[kThreads][P];
-  __shared__ uint64_t sKb[P];
-  __shared__ unsigned long long s_n;
-  __shared__ unsigned short s_ls[MAXLS];  // line starts (stage-relative)
-  __shared__ int s_wsum[kThreads / 64];
-  const int64_t s0 = (int64_t)blockIdx.x * SEG;
-  const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
-  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
-  const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
-  const int n = (int)(w1 - w0);
-  // stage [w0, w1): aligned 16-byte loads in the middle, single bytes at the
-  // two ragged ends, so that no byte outside [buf, buf + nbytes) is read
-  const uintptr_t lo = (uintptr_t)(a.buf + w0), hi = (uintptr_t)(a.buf + w1);
+// Copies the text [w0, w0 + n) of buf into LDS (padded 16 bytes per 256):
+// aligned 16-byte loads in the middle, single bytes at the two ragged ends,
+// so that no byte outside [buf + w0, buf + w0 + n) is read.
+__device__ inline void stage_text(const char* buf, int64_t w0, int n, unsigned char* s_buf) {
+  const uintptr_t lo = (uintptr_t)(buf + w0), hi = (uintptr_t)(buf + w0 + n);
   const uintptr_t alo = (lo + 15) & ~(uintptr_t)15, ahi = hi & ~(uintptr_t)15;
   if (alo < ahi) {
     const int head = (int)(alo - lo);
@@ -445,58 +434,25 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
 #pragma unroll
       for (int k = 0; k < 16; ++k) s_buf[pad(head + 16 * v + k)] = qb[k];
     }
-    for (int k = threadIdx.x; k < head; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+    for (int k = threadIdx.x; k < head; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
     const int tail0 = head + 16 * nvec;
-    for (int k = tail0 + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+    for (int k = tail0 + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
   } else {
-    for (int k = threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)a.buf[w0 + k];
+    for (int k = threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
   }
-  if (threadIdx.x == 0) s_n = 0;
-  __syncthreads();
-  const Stage S{s_buf, w0, n, (int)(min(a.nend, w0 + (int64_t)n) - w0)};
-  const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);  // relative positions
+}
 
-  // shift words (int64 for integer columns, FP64 bits otherwise): the row of
-  // the workgroup's first line, zeros if it does not parse; set below
-  uint64_t K64[P];
-#pragma unroll
-  for (int c = 0; c < P; ++c) K64[c] = 0;
-
-  acc::Acc<P> A;
-  A.zero();
-  uint32_t bad = 0;
-  unsigned long long nrows = 0;
-  int first_bad = INT32_MAX;
-  Cur C(S);
-  auto add_row = [&](const uint64_t* row) {
-    double d[P];
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      const uint64_t b = row[c];
-      d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
-                                      : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
-    }
-    A.add(d);
-    ++nrows;
-  };
-  auto take_line = [&](int L) -> int {  // parses and accumulates one line; returns the next position
-    uint64_t* row = s_row[threadIdx.x];
-    int bad_at = INT32_MAX;
-    const int end = parse_line(a, C, L, row, &bad_at);
-    if (end >= 0) {
-      add_row(row);
-      return end + 1;
-    }
-    first_bad = min(first_bad, bad_at);
-    return (-1 - end) + 1;
-  };
-
-  // line starts in [s0, s1): a position after '\n' (or the stream start).
-  // Thread t finds the newlines of its SLICE positions in one pass of 16-byte
-  // LDS reads, keeping them as a bit mask (a '\n' byte is a zero byte of
-  // v ^ 0x0a0a0a0a); a workgroup scan of the counts places them, and thread t
-  // then parses lines t, t + 256, ...: the lanes of a wave walk the same
-  // fields of different lines side by side.
+// Line starts of a workgroup's segment [s0r, s1r) (stage-relative; a line
+// starts after '\n' or at the stream start).  Thread t finds the newlines of
+// its SLICE positions in one pass of 16-byte LDS reads, keeping them as a bit
+// mask (a '\n' byte is a zero byte of v ^ 0x0a0a0a0a); a workgroup scan of the
+// counts places them in s_ls in stream order when they fit (<= MAXLS).
+// Returns their number; *c0, *c1 receive this thread's slice and *before the
+// number of line starts in earlier slices (the index of its first line).
+// Contains barriers: every thread of the workgroup calls it.
+__device__ inline int line_starts(const unsigned char* s_buf, int64_t w0, int s0r, int s1r,
+                                  unsigned short* s_ls, int* s_wsum, int* c0_out, int* c1_out,
+                                  int* before_out) {
   static_assert(SLICE * kThreads == SEG && SLICE % 16 == 0, "one slice per thread");
   constexpr int NV = SLICE / 16 + 1;         // 16-byte reads per slice (it may start mid-vector)
   constexpr int NM = (16 * NV + 31) / 32;    // 32-bit mask words
@@ -551,20 +507,85 @@ __global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
     if (k < wv) before += s_wsum[k];
     total += s_wsum[k];
   }
-  if (total <= MAXLS) {
-    if (c0 < c1) {
-      int at = before;
-      if (w0 + c0 == 0) s_ls[at++] = (unsigned short)c0;
+  if (total <= MAXLS && c0 < c1) {
+    int at = before;
+    if (w0 + c0 == 0) s_ls[at++] = (unsigned short)c0;
 #pragma unroll
-      for (int j = 0; j < NM; ++j) {
-        uint32_t m = nl[j];
-        while (m) {
-          s_ls[at++] = (unsigned short)(mb + 32 * j + __builtin_ctz(m) + 1);
-          m &= m - 1;
-        }
+    for (int j = 0; j < NM; ++j) {
+      uint32_t m = nl[j];
+      while (m) {
+        s_ls[at++] = (unsigned short)(mb + 32 * j + __builtin_ctz(m) + 1);
+        m &= m - 1;
       }
     }
-    __syncthreads();
+  }
+  __syncthreads();
+  *c0_out = c0;
+  *c1_out = c1;
+  *before_out = before;
+  return total;
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
+  __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
+  __shared__ uint64_t s_row[kThreads][P];
+  __shared__ uint64_t sKb[P];
+  __shared__ unsigned long long s_n;
+  __shared__ unsigned short s_ls[MAXLS];  // line starts (stage-relative)
+  __shared__ int s_wsum[kThreads / 64];
+  const int64_t s0 = (int64_t)blockIdx.x * SEG;
+  const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
+  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
+  const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
+  const int n = (int)(w1 - w0);
+  stage_text(a.buf, w0, n, s_buf);
+  if (threadIdx.x == 0) s_n = 0;
+  __syncthreads();
+  const Stage S{s_buf, w0, n, (int)(min(a.nend, w0 + (int64_t)n) - w0)};
+  const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);  // relative positions
+
+  // shift words (int64 for integer columns, FP64 bits otherwise): the row of
+  // the workgroup's first line, zeros if it does not parse; set below
+  uint64_t K64[P];
+#pragma unroll
+  for (int c = 0; c < P; ++c) K64[c] = 0;
+
+  acc::Acc<P> A;
+  A.zero();
+  uint32_t bad = 0;
+  unsigned long long nrows = 0;
+  int first_bad = INT32_MAX;
+  Cur C(S);
+  auto add_row = [&](const uint64_t* row) {
+    double d[P];
+#pragma unroll
+    for (int c = 0; c < P; ++c) {
+      const uint64_t b = row[c];
+      d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
+                                      : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
+    }
+    A.add(d);
+    ++nrows;
+  };
+  auto take_line = [&](int L) -> int {  // parses and accumulates one line; returns the next position
+    uint64_t* row = s_row[threadIdx.x];
+    int bad_at = INT32_MAX;
+    const int end = parse_line(a, C, L, row, &bad_at);
+    if (end >= 0) {
+      add_row(row);
+      return end + 1;
+    }
+    first_bad = min(first_bad, bad_at);
+    return (-1 - end) + 1;
+  };
+
+  // line starts in [s0, s1); thread t then parses lines t, t + 256, ...: the
+  // lanes of a wave walk the same fields of different lines side by side
+  int c0, c1, before;
+  const int total = line_starts(s_buf, w0, s0r, s1r, s_ls, s_wsum, &c0, &c1, &before);
+  (void)before;
+  if (total <= MAXLS) {
     // the first pass (lines 0..255) parses only; line 0 is the workgroup's
     // first line, whose row (copied by thread 0 before the barrier) is the
     // block shift
@@ -633,6 +654,143 @@ __global__ void k_last_newline(const char* buf, int64_t n, int64_t* out) {
     __syncthreads();
   }
   if (threadIdx.x == 0) *out = (int64_t)best;
+}
+
+// ---- CSV -> fixed-width binary rows ------------------------------------------
+
+// Line starts per segment ([s0, s1) as in k_text), read from global memory.
+__global__ __launch_bounds__(kThreads) void k_seg_lines(const char* buf, int64_t nend, int64_t* counts) {
+  __shared__ int s_sum[kThreads / 64];
+  const int64_t s0 = (int64_t)blockIdx.x * SEG;
+  const int64_t s1 = min(s0 + (int64_t)SEG, nend);
+  // newlines at m in [max(s0 - 1, 0), s1 - 1) start the lines after s0
+  const int64_t ma = s0 > 0 ? s0 - 1 : 0, mz = s1 - 1;
+  int mine = 0;
+  for (int64_t m = ma + threadIdx.x; m < mz; m += kThreads) mine += buf[m] == '\n';
+  if (s0 == 0 && threadIdx.x == 0 && s1 > 0) ++mine;  // the stream's first line
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) mine += __shfl_down(mine, d, 64);
+  if ((threadIdx.x & 63) == 0) s_sum[threadIdx.x >> 6] = mine;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int t = 0;
+    for (int k = 0; k < kThreads / 64; ++k) t += s_sum[k];
+    counts[blockIdx.x] = t;
+  }
+}
+
+// In-place exclusive scan of n counts (one workgroup); total -> counts[n].
+__global__ __launch_bounds__(1024) void k_scan_counts(int64_t* counts, int64_t n) {
+  __shared__ int64_t s_part[1024];
+  __shared__ int64_t s_carry;
+  if (threadIdx.x == 0) s_carry = 0;
+  __syncthreads();
+  for (int64_t b0 = 0; b0 < n; b0 += 1024) {
+    const int64_t i = b0 + threadIdx.x;
+    const int64_t v = i < n ? counts[i] : 0;
+    s_part[threadIdx.x] = v;
+    __syncthreads();
+    for (int d = 1; d < 1024; d <<= 1) {
+      const int64_t y = threadIdx.x >= (unsigned)d ? s_part[threadIdx.x - d] : 0;
+      __syncthreads();
+      s_part[threadIdx.x] += y;
+      __syncthreads();
+    }
+    const int64_t excl = s_carry + s_part[threadIdx.x] - v;
+    if (i < n) counts[i] = excl;
+    __syncthreads();
+    if (threadIdx.x == 1023) s_carry += s_part[1023];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) counts[n] = s_carry;
+}
+
+struct ConvArgs {
+  Args t;                    // text, its line limit, p, integer mask, offsets, status
+  const int64_t* seg_base;   // first output row of each segment
+  char* out[16];             // column c of row r at out[c] + r * stride[c]
+  int64_t stride[16];
+  int32_t dtype[16];         // STATS_I32 / STATS_I64 / STATS_F64
+};
+
+// One parsed field into its binary column; false when the value does not fit
+// the column's type (an integer beyond int32, or beyond 2^53 for FP64).
+__device__ inline bool store_field(const ConvArgs& a, int c, int64_t r, uint64_t bits, bool is_int) {
+  char* dst = a.out[c] + r * a.stride[c];
+  switch (a.dtype[c]) {
+    case STATS_I32: {
+      const int64_t v = (int64_t)bits;
+      if (v < INT32_MIN || v > INT32_MAX) return false;
+      *(int32_t*)dst = (int32_t)v;
+      return true;
+    }
+    case STATS_I64: *(int64_t*)dst = (int64_t)bits; return true;
+    default: {
+      if (is_int) {
+        const int64_t v = (int64_t)bits;
+        if (v > ((int64_t)1 << 53) || v < -((int64_t)1 << 53)) return false;
+        *(double*)dst = (double)v;
+      } else {
+        *(uint64_t*)dst = bits;
+      }
+      return true;
+    }
+  }
+}
+
+template <int P>
+__global__ __launch_bounds__(kThreads) void k_text_convert(ConvArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
+  __shared__ uint64_t s_row[kThreads][P];
+  __shared__ unsigned short s_ls[MAXLS];
+  __shared__ int s_wsum[kThreads / 64];
+  const Args& t = a.t;
+  const int64_t s0 = (int64_t)blockIdx.x * SEG;
+  const int64_t s1 = min(s0 + (int64_t)SEG, t.nend);
+  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
+  const int64_t w1 = min(s1 + (int64_t)MAXLINE, t.nbytes);
+  const int n = (int)(w1 - w0);
+  stage_text(t.buf, w0, n, s_buf);
+  __syncthreads();
+  const Stage S{s_buf, w0, n, (int)(min(t.nend, w0 + (int64_t)n) - w0)};
+  const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);
+  Cur C(S);
+  int c0, c1, before;
+  const int total = line_starts(s_buf, w0, s0r, s1r, s_ls, s_wsum, &c0, &c1, &before);
+  const int64_t base = a.seg_base[blockIdx.x];
+  int first_bad = INT32_MAX;
+  // parses line L (k-th of the segment) into output row base + k
+  auto put_line = [&](int L, int k) -> int {
+    uint64_t* row = s_row[threadIdx.x];
+    int bad_at = INT32_MAX;
+    const int end = parse_line(t, C, L, row, &bad_at);
+    if (end < 0) {
+      first_bad = min(first_bad, L);  // reported by the line's first byte
+      return -end;  // (-1 - e) + 1: past the offending line
+    }
+#pragma unroll
+    for (int c = 0; c < P; ++c)
+      if (!store_field(a, c, base + k, row[c], (t.intmask >> c) & 1u)) first_bad = min(first_bad, L);
+    return end + 1;
+  };
+  if (total <= MAXLS) {
+    for (int k = threadIdx.x; k < total; k += kThreads) (void)put_line((int)s_ls[k], k);
+  } else {
+    // too many lines for the table: each thread walks its own slice
+    int L = c0, k = before;
+    if (w0 + L > 0)
+      while (L < c1 && C.at(L - 1) != '\n') ++L;
+    while (L < c1) L = put_line(L, k++);
+  }
+  if (first_bad != INT32_MAX) {
+    atomicMin(&t.status->parse_off, (unsigned long long)(t.base_off + w0 + first_bad));
+    atomicOr(&t.status->bits, ST_PARSE);
+  }
+}
+
+template <int P>
+void launch_convert_p(const ConvArgs& a, int64_t nblocks, hipStream_t s) {
+  hipLaunchKernelGGL(k_text_convert<P>, dim3((unsigned)nblocks), dim3(kThreads), 0, s, a);
 }
 
 template <int P>
@@ -710,6 +868,7 @@ extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbyt
   if (!h) return fail(STATS_E_ARG, "handle is NULL");
   if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
   if (h->ngroups) return fail(STATS_E_STATE, "groups handle: text input is not supported");
+  if (h->flags & STATS_CFG_PAIRWISE) return fail(STATS_E_STATE, "pairwise handle: text input is not supported");
   if (!bytes_consumed) return fail(STATS_E_ARG, "bytes_consumed is NULL");
   *bytes_consumed = 0;
   if (nbytes < 0) return fail(STATS_E_ARG, "nbytes < 0");
@@ -749,6 +908,116 @@ extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbyt
     if (e != hipSuccess) return hip_fail(h, e, "text ingest");
   }
   h->text_offset += nend;
+  *bytes_consumed = nend;
+  return STATS_OK;
+}
+
+extern "C" int stats_text_to_binary(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
+                                    int32_t is_last, void* const* out_planes, int64_t max_rows,
+                                    int64_t* rows_out, int64_t* bytes_consumed) {
+  if (!h) return fail(STATS_E_ARG, "handle is NULL");
+  if (h->poisoned) return fail(STATS_E_STATE, "handle is poisoned by an earlier HIP error");
+  if (h->ngroups) return fail(STATS_E_STATE, "groups handle: text conversion is not supported");
+  if (!bytes_consumed || !rows_out) return fail(STATS_E_ARG, "rows_out or bytes_consumed is NULL");
+  *bytes_consumed = 0;
+  *rows_out = 0;
+  if (nbytes < 0 || max_rows < 0) return fail(STATS_E_ARG, "nbytes or max_rows < 0");
+  const int p = h->p;
+  if (p > 16) return fail(STATS_E_ARG, "text conversion supports p <= 16");
+  for (int c = 0; c < p; ++c) {
+    const stats_column& col = h->cols[c];
+    if (col.dtype == STATS_F32) return fail(STATS_E_ARG, "text conversion writes I32, I64 or F64 columns");
+    if (!h->intf[c] && col.dtype != STATS_F64)
+      return fail(STATS_E_ARG, "a decimal (non-integer) column must be stored as F64");
+  }
+  if (nbytes == 0) return STATS_OK;
+  if (!buf || !out_planes) return fail(STATS_E_ARG, "buf or out_planes is NULL");
+  for (int c = 0; c < p; ++c)
+    if (!out_planes[h->cols[c].plane]) return fail(STATS_E_ARG, "an output plane is NULL");
+  DeviceGuard g(h->device);
+  if (!g.ok) return fail(STATS_E_HIP, "hipSetDevice failed");
+  const char* dbuf = buf;
+  hipError_t e;
+  if (mem_kind == STATS_MEM_HOST || mem_kind == STATS_MEM_HOST_PINNED) {
+    int rc = ensure_dev(h, &h->aux_dev, &h->aux_cap, (size_t)nbytes);
+    if (rc) return rc;
+    e = hipMemcpyAsync(h->aux_dev, buf, (size_t)nbytes, hipMemcpyHostToDevice, h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "copying text to the device");
+    dbuf = (const char*)h->aux_dev;
+  } else if (mem_kind != STATS_MEM_DEVICE) {
+    return fail(STATS_E_ARG, "unknown mem_kind");
+  }
+  const int64_t nseg_max = (nbytes + SEG - 1) / SEG;
+  // scratch: per-segment counts / first rows (nseg + 1), the last line end,
+  // and a status word of its own (the handle's statistics are not touched)
+  const size_t cnt_bytes = (size_t)(nseg_max + 1) * 8;
+  const size_t need = (cnt_bytes + 255) / 256 * 256 + 256;
+  int rc = ensure_dev(h, &h->conv_dev, &h->conv_cap, need);
+  if (rc) return rc;
+  int64_t* counts = (int64_t*)h->conv_dev;
+  char* tailp = (char*)h->conv_dev + (cnt_bytes + 255) / 256 * 256;
+  int64_t* nend_dev = (int64_t*)tailp;
+  DevStatus* cst = (DevStatus*)(tailp + 64);
+  static const DevStatus init = {0u, 0u, ~0ull};
+  e = hipMemcpyAsync(cst, &init, sizeof init, hipMemcpyHostToDevice, h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "clearing the conversion status");
+  int64_t nend = nbytes;
+  if (!is_last) {
+    hipLaunchKernelGGL(k_last_newline, dim3(1), dim3(1024), 0, h->stream, dbuf, nbytes, nend_dev);
+    e = hipGetLastError();
+    if (e == hipSuccess) e = hipMemcpyAsync(&nend, nend_dev, 8, hipMemcpyDeviceToHost, h->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "finding the last line end");
+  }
+  const int64_t nseg = (nend + SEG - 1) / SEG;
+  if (nseg == 0) return STATS_OK;
+  hipLaunchKernelGGL(k_seg_lines, dim3((unsigned)nseg), dim3(kThreads), 0, h->stream, dbuf, nend, counts);
+  e = hipGetLastError();
+  if (e == hipSuccess) {
+    hipLaunchKernelGGL(k_scan_counts, dim3(1), dim3(1024), 0, h->stream, counts, nseg);
+    e = hipGetLastError();
+  }
+  int64_t total = 0;
+  if (e == hipSuccess) e = hipMemcpyAsync(&total, counts + nseg, 8, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "counting lines");
+  if (total > max_rows)
+    return fail(STATS_E_ARG, "the chunk holds " + std::to_string(total) + " lines, the output " +
+                                 std::to_string(max_rows) + " rows");
+  ConvArgs a;
+  memset(&a, 0, sizeof a);
+  a.t.buf = dbuf;
+  a.t.nbytes = nbytes;
+  a.t.nend = nend;
+  a.t.p = p;
+  a.t.base_off = h->text_offset;
+  a.t.status = cst;
+  for (int c = 0; c < p; ++c)
+    if (h->intf[c]) a.t.intmask |= 1u << c;
+  a.seg_base = counts;
+  for (int c = 0; c < p; ++c) {
+    const stats_column& col = h->cols[c];
+    a.out[c] = (char*)out_planes[col.plane] + col.byte_offset;
+    a.stride[c] = h->row_stride[col.plane];
+    a.dtype[c] = col.dtype;
+  }
+  switch (p) {
+#define ST_CASE(PP) \
+  case PP: launch_convert_p<PP>(a, nseg, h->stream); break;
+    ST_CASE(1) ST_CASE(2) ST_CASE(3) ST_CASE(4) ST_CASE(5) ST_CASE(6) ST_CASE(7) ST_CASE(8)
+    ST_CASE(9) ST_CASE(10) ST_CASE(11) ST_CASE(12) ST_CASE(13) ST_CASE(14) ST_CASE(15) ST_CASE(16)
+#undef ST_CASE
+  }
+  e = hipGetLastError();
+  DevStatus st{};
+  if (e == hipSuccess) e = hipMemcpyAsync(&st, cst, sizeof st, hipMemcpyDeviceToHost, h->stream);
+  if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
+  if (e != hipSuccess) return hip_fail(h, e, "text conversion");
+  h->text_offset += nend;
+  if (st.bits & ST_PARSE)
+    return fail(STATS_E_PARSE, "malformed or out-of-range field in the line starting at byte offset " +
+                                   std::to_string((unsigned long long)st.parse_off));
+  *rows_out = total;
   *bytes_consumed = nend;
   return STATS_OK;
 }
