@@ -34,36 +34,51 @@ sys.path.insert(0, ROOT)
 METRIC = "rows/sec and HBM GB/s (fraction of peak) for fused colsum+XᵀX; cov rel. error"
 HBM_PEAK_GBS = 8000.0
 BF16_PEAK_TFLOPS = 2500.0
+I8_PEAK_TOPS = 5000.0
 FP64_PEAK_TFLOPS = 78.6
-PMC_FILE = os.path.join(ROOT, "profiles", "accum_small_p_table1_2e9_pmc.json")
-# sources of the narrow-table planes kernel whose counters are on file
-KERNEL_SRCS = [os.path.join(ROOT, "paper_2604_23826_amd", "csrc", f)
-               for f in ("accum_common.hpp", "accum_planes.hpp")]
+# rocprofv3 FETCH_SIZE / WRITE_SIZE summaries on file, per workload: the
+# file and the kernel sources the counters were taken on
+_CSRC = os.path.join(ROOT, "paper_2604_23826_amd", "csrc")
+PMC = {
+    "share": ("accum_small_p_table1_2e9_pmc.json", ("accum_common.hpp", "accum_planes.hpp")),
+    "wide": ("wide_i8_fp32_1e8x256_pmc.json", ("wide_syrk.hip", "wide.hpp")),
+    "text": ("text_csv_1e8_lines_pmc.json", ("text.hip", "accum_common.hpp")),
+}
 
 
 def log(*a):
     print(*a, file=sys.stderr, flush=True)
 
 
-def kernel_sha():
+def kernel_sha(workload="share"):
     h = hashlib.sha256()
-    for p in KERNEL_SRCS:
-        with open(p, "rb") as f:
+    for name in PMC[workload][1]:
+        with open(os.path.join(_CSRC, name), "rb") as f:
             h.update(f.read())
     return h.hexdigest()[:16]
 
 
-def traffic_from_profile(rows_per_launch):
-    """HBM bytes per launch from the committed rocprofv3 counter summary, or
-    None when absent or taken on a different kernel source."""
+def traffic_from_profile(units_per_launch, workload="share"):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (bytes per row, or per text byte), or None when absent or taken on a
+    different kernel source."""
     try:
-        with open(PMC_FILE) as f:
+        with open(os.path.join(ROOT, "profiles", PMC[workload][0])) as f:
             d = json.load(f)
     except (OSError, ValueError):
         return None
-    if d.get("kernel_source_sha") != kernel_sha():
+    if d.get("kernel_source_sha") != kernel_sha(workload):
         return None
-    return d["hbm_bytes_per_row"] * rows_per_launch
+    return d["hbm_bytes_per_unit"] * units_per_launch
+
+
+def calibrate_copy(torch):
+    """A plain 1 GiB device-to-device copy (reads 1 GiB, writes 1 GiB): its
+    FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes."""
+    a = torch.empty(1 << 30, dtype=torch.uint8, device="cuda:0")
+    b = torch.empty_like(a)
+    b.copy_(a)
+    torch.cuda.synchronize()
 
 
 def base_json(args, value, unit, ms_per_step, dtype, config):
@@ -244,7 +259,7 @@ def run_share(args, L, torch, datagen):
     launches = n1 - n0
     rows_per_launch = N * args.steps / max(launches, 1)
     roof = hbm_roofline("accum_small_p (p=10, int32x9 + fp64 planes)", N * args.steps * bpr, ms1 - ms0,
-                        launches, rows_per_launch * bpr, traffic_from_profile(rows_per_launch))
+                        launches, rows_per_launch * bpr, traffic_from_profile(rows_per_launch, "share"))
     if kind == L.STATS_MEM_DEVICE:
         add_measured_read(roof, L, bases, [N * s for s in itemsz], stream)
     log(f"step {ms_per_step:.2f} ms, {rows_per_s:.3e} rows/s, kernel {roof['achieved']:.0f} GB/s")
@@ -263,11 +278,7 @@ def run_share(args, L, torch, datagen):
             cpu.pop("_rows")
             cpu.pop("_ref_cov")
     if args.calibrate_copy:
-        # a plain copy of known size for scaling the HBM traffic counters
-        a = torch.empty(1 << 30, dtype=torch.uint8, device=dev)
-        b = torch.empty_like(a)
-        b.copy_(a)
-        torch.cuda.synchronize()
+        calibrate_copy(torch)
     L.stats_close(h)
     out = base_json(args, rows_per_s, "rows/s", ms_per_step, "f64",
                     {"workload": ("table1_share_2e9_rows" if N == 2_000_000_000 else f"table1_{N}_rows") +
@@ -363,7 +374,7 @@ def run_wide(args, L, torch, datagen):
     torch.cuda.synchronize()
     cols = [(L.STATS_I32, 1, 0, L.STATS_COL_IDENTIFIER)] + [(L.STATS_F32, 0, 4 * j, 0) for j in range(256)]
     res = {}
-    for mode, prec in (("split", L.STATS_PREC_SPLIT_BF16), ("fp64", L.STATS_PREC_FP64)):
+    for mode, prec in (("split", L.STATS_PREC_SPLIT), ("fp64", L.STATS_PREC_FP64)):
         h = L.stats_open(L.make_config(cols, [1024, 4], stream=stream, timing=True, precision=prec))
         steps = args.steps if mode == "split" else max(1, min(args.steps, 2))
         for _ in range(min(args.warmup, 1)):
@@ -398,20 +409,26 @@ def run_wide(args, L, torch, datagen):
     T = p * (p + 1) // 2
     sp = res["split"]
     # algorithmic work per row: 1028 bytes read; p(p+1) = 2T flops (the upper
-    # triangle of x x^T); the split kernel issues nine BF16 digit products per
-    # pair, 9 x 2T flops, on the matrix cores
+    # triangle of x x^T).  The split kernel issues nine int8 digit products
+    # on 32 x 32 tiles: 48 tile products per row of 256 columns (3 group
+    # pairs x 2 halves x 8 waves; the diagonal pairs' 10 tiles in 16 wave
+    # slots), 9 x 2 x 48 x 1024 integer operations per row
     bytes_row = 4 * 256 + 4
     launches = max(sp["launches_per_pass"], 1)
-    out = base_json(args, N / (sp["accumulate_ms"] / 1e3), "rows/s", sp["accumulate_ms"], "bf16x3",
+    out = base_json(args, N / (sp["accumulate_ms"] / 1e3), "rows/s", sp["accumulate_ms"], "i8x3",
                     {"workload": f"gauss_fp32_{N}x256_plus_int32_id", "rows": N, "p": p,
-                     "bytes_per_row": bytes_row, "step": "reset + accumulate (split BF16 matrix cores) + sync"})
-    out["roofline"] = hbm_roofline("k_syrk_split (split BF16 digits on the matrix cores)", N * bytes_row,
-                                   sp["syrk_ms"], int(round(launches)), N * bytes_row / launches)
+                     "bytes_per_row": bytes_row,
+                     "step": "reset + accumulate (int8 digit products on the matrix cores) + sync"})
+    out["roofline"] = hbm_roofline("k_syrk_i8 (int8 digits on the matrix cores)", N * bytes_row,
+                                   sp["syrk_ms"], int(round(launches)), N * bytes_row / launches,
+                                   traffic_from_profile(N / launches, "wide"))
     algo = 2.0 * N * T / (sp["syrk_ms"] / 1e3) / 1e12
-    out["roofline"]["mfma"] = {"algorithmic_tflops": round(algo, 1), "frac_of_bf16_peak": round(algo / BF16_PEAK_TFLOPS, 4),
-                               "issued_digit_product_tflops": round(9 * algo, 1),
-                               "issued_frac_of_bf16_peak": round(9 * algo / BF16_PEAK_TFLOPS, 4),
-                               "algorithmic_flops_per_row": 2 * T}
+    issued = 9 * 2 * 48 * 1024 * N / (sp["syrk_ms"] / 1e3) / 1e12
+    out["roofline"]["mfma"] = {"algorithmic_tflops": round(algo, 1),
+                               "issued_int8_tops": round(issued, 1),
+                               "issued_frac_of_int8_peak": round(issued / I8_PEAK_TOPS, 4),
+                               "algorithmic_flops_per_row": 2 * T,
+                               "issued_int8_ops_per_row": 9 * 2 * 48 * 1024}
     out["hbm_gbs"] = round(N * 1028 / (sp["accumulate_ms"] / 1e3) / 1e9, 1)
     out["fp64_path"] = {"accumulate_ms": round(res["fp64"]["accumulate_ms"], 2),
                         "syrk_ms": round(res["fp64"]["syrk_ms"], 2),
@@ -420,7 +437,49 @@ def run_wide(args, L, torch, datagen):
     out["split_vs_fp64"] = {"speedup": round(res["fp64"]["accumulate_ms"] / sp["accumulate_ms"], 3),
                             "cov_rel_err": err, "eigval_rel_err": lam_err}
     out["finalize_ms_p256"] = round(sp["finalize_ms"], 1)
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"], out["vs_oracle_prefix"] = wide_oracle_prefix(
+            args, L, torch, x, ident, cols, stream, min(N, args.wide_prefix_rows))
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     return out
+
+
+def wide_oracle_prefix(args, L, torch, x, ident, cols, stream, S):
+    """The oracle on the first S rows of the wide table (all usable host
+    threads, at most 16; both passes + exact-rational finalize, timed), and
+    each mode's results on the same rows against it, per output: covariance
+    (largest |difference| / sqrt(cov_ii cov_jj)), correlation and mean (in
+    standard deviations) as largest absolute differences, eigenvalues
+    relative to the largest."""
+    import numpy as np
+    import oracle
+    info = host_info()
+    threads = max(1, min(16, info["usable_cpus"] or 1))
+    xh = x[:S].cpu().numpy()
+    ih = ident[:S].cpu().numpy()
+    hcols = [ih] + [xh[:, j] for j in range(xh.shape[1])]
+    p = len(hcols)
+    t0 = time.perf_counter()
+    st = oracle.sufficient_stats(hcols, [True] + [False] * (p - 1), threads=threads)
+    ref = oracle.finalize(st, mask=range(1, p))
+    t1 = time.perf_counter()
+    errs = {}
+    for mode, prec in (("split", L.STATS_PREC_SPLIT), ("fp64", L.STATS_PREC_FP64)):
+        h = L.stats_open(L.make_config(cols, [1024, 4], stream=stream, precision=prec))
+        L.stats_accumulate(h, [x, ident], S)
+        fin = L.stats_finalize(h, p)
+        L.stats_close(h)
+        sd = np.sqrt(np.diag(ref["cov"]))
+        errs[mode] = {"cov": cov_err(fin["cov"], ref["cov"]),
+                      "corr": float(np.max(np.abs(fin["corr"] - ref["corr"]))),
+                      "eigval": float(np.max(np.abs(fin["eigval"] - ref["eigval"])) / np.max(ref["eigval"])),
+                      "mean": float(np.max(np.abs(fin["mean"] - ref["mean"]) / sd))}
+    log(f"oracle on {S} rows: {t1 - t0:.1f} s; split vs oracle {errs['split']}")
+    cpu = {"value": round(S / (t1 - t0), 1), "unit": "rows/s", "cores": threads, "kind": "oracle",
+           "sample": f"first {S} rows of the same table on {threads} threads "
+                     f"(both passes + finalize, {t1 - t0:.1f} s)", "host": info}
+    return cpu, {"rows": S, **errs}
 
 
 # ---- groups: 4096 groups of 32 FP64 columns, in waves -------------------------
@@ -568,10 +627,14 @@ def run_text(args, L, torch, datagen):
                     {"workload": f"table1_csv_{N}_lines_1GiB_chunks", "rows": N, "p": 10,
                      "text_bytes": nbytes, "step": "reset + parse/accumulate all chunks + finalize"})
     out["text_gbs"] = round(nbytes / el / 1e9, 2)
+    launches = max(n1 - n0, 1)
     out["roofline"] = add_measured_read(
         hbm_roofline("k_text (parse fused with colsum + X^T X)", nbytes * args.steps,
-                     ms1 - ms0, n1 - n0, nbytes * args.steps / max(n1 - n0, 1)),
+                     ms1 - ms0, n1 - n0, nbytes * args.steps / launches,
+                     traffic_from_profile(nbytes * args.steps / launches, "text")),
         L, [base], [nbytes], stream)
+    if args.calibrate_copy:
+        calibrate_copy(torch)
     return out
 
 
@@ -589,6 +652,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--host-staged", action="store_true")
     ap.add_argument("--calibrate-copy", action="store_true")
+    ap.add_argument("--wide-prefix-rows", type=int, default=1 << 18,
+                    help="wide: rows the oracle reduces for cpu_baseline and the error check")
     args = ap.parse_args()
     args.rows_given = args.rows is not None
     if args.rows is None:

@@ -81,11 +81,18 @@ enum { STATS_MEM_DEVICE = 0, STATS_MEM_HOST_PINNED = 1, STATS_MEM_HOST = 2 };
 
 /* Arithmetic of the cross-product pass for wide tables (p > 16). */
 enum {
-  STATS_PREC_FP64 = 0,       /* FP64 throughout */
-  STATS_PREC_SPLIT_BF16 = 1, /* BF16 slices on MFMA, FP32 windows, FP64 merge */
-  STATS_PREC_AUTO = 2        /* p <= 16: FP64; wider: split BF16 when every
-                                column is FP32 or int32, else FP64 */
+  STATS_PREC_FP64 = 0,  /* FP64 throughout */
+  STATS_PREC_SPLIT = 1, /* fixed-point digits of the block-shifted values on
+                           the matrix cores, exact integer (FP32 row-major
+                           layout: int8 digits, blocks outside the sampled
+                           grid redone in FP64) or exact FP32 (other layouts:
+                           BF16 digits, 2^-27 of the block range) sums,
+                           FP64 merge */
+  STATS_PREC_AUTO = 2   /* p <= 16: FP64; wider: split when the FP32
+                           row-major int8 kernel applies, else FP64 */
 };
+/* Former name of STATS_PREC_SPLIT. */
+enum { STATS_PREC_SPLIT_BF16 = STATS_PREC_SPLIT };
 
 /* Configuration flags. */
 enum {
@@ -186,7 +193,10 @@ int stats_accumulate_file(stats_ctx* h, const char* path, int64_t offset, int64_
  * its parsing cost: section "Data Representation and Sufficient
  * Statistics").  Lines must end in '\n'; one row per line, p fields
  * separated by ',', integer columns in decimal, floating columns as decimal
- * floating-point text (parsed with correct rounding).  Only complete lines
+ * floating-point text (parsed with correct rounding; magnitudes below 1e73
+ * with the last written digit's decimal exponent >= -57 always convert,
+ * fields beyond about 2.3e74 or with a later last digit are malformed).
+ * Only complete lines
  * are consumed unless is_last != 0, when a final unterminated line counts
  * too; *bytes_consumed receives the bytes used (the caller passes the rest
  * again at the front of the next chunk).  A malformed field gives

@@ -39,7 +39,8 @@ STATS_E_INEXACT, STATS_E_PARSE, STATS_E_MISMATCH, STATS_E_IO = -5, -6, -7, -8
 STATS_I32, STATS_I64, STATS_F32, STATS_F64 = 1, 2, 3, 4
 STATS_COL_INTEGER, STATS_COL_IDENTIFIER = 1, 2
 STATS_MEM_DEVICE, STATS_MEM_HOST_PINNED, STATS_MEM_HOST = 0, 1, 2
-STATS_PREC_FP64, STATS_PREC_SPLIT_BF16, STATS_PREC_AUTO = 0, 1, 2
+STATS_PREC_FP64, STATS_PREC_SPLIT, STATS_PREC_AUTO = 0, 1, 2
+STATS_PREC_SPLIT_BF16 = STATS_PREC_SPLIT  # former name
 STATS_CFG_TIMING = 1
 STATS_CFG_PAIRWISE = 2
 STATS_NOALLOC_SCRATCH_BYTES = 8 << 20

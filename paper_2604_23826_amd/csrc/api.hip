@@ -514,7 +514,7 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
 int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
   if (h->flags & STATS_CFG_PAIRWISE) return accumulate_pairwise(h, planes, nrows);
   if (h->p <= 16) return accumulate_device_small(h, planes, nrows);
-  if (h->p <= 32 && h->precision != STATS_PREC_SPLIT_BF16 && aos_rows_layout(h, planes, 256))
+  if (h->p <= 32 && h->precision != STATS_PREC_SPLIT && aos_rows_layout(h, planes, 256))
     return accumulate_aos_rows(h, planes, nrows, h->block_rows ? h->block_rows : auto_block_rows(nrows), 256);
   return accumulate_device_wide(h, planes, nrows);
 }

@@ -17,8 +17,11 @@
 // digits), parsed exactly; other columns are decimal numbers (optional sign,
 // digits with an optional point, optional exponent), converted to the nearest
 // FP64 value: the decimal significand w and exponent q give w * 10^q, formed
-// as an exact 256-bit integer ratio and divided once with correct rounding
-// (values between about 1e-57 and 1e75).  A malformed field marks
+// as an exact 256-bit integer ratio and divided once with correct rounding.
+// The ratio's range: every |value| below 1e73 whose last written digit has
+// exponent q >= -57 converts; a field beyond 2^247 (about 2.3e74) or with
+// q < -57 is refused as malformed (in between, by the significand's bit
+// length).  A malformed field marks
 // the handle (STATS_E_PARSE, smallest byte offset) and its row is skipped.
 #include <cstring>
 

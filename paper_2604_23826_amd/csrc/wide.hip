@@ -225,6 +225,19 @@ __global__ __launch_bounds__(kThreads) void k_seg_f64(Args a, SegArgs g) {
 
 __global__ void k_zero_counter(unsigned long long* c) { *c = 0ull; }
 
+// Blocks of the int8 split kernel whose values left their grids (or were not
+// finite): the same (block, super-tile) grid as k_wide_f64, flagged blocks only.
+template <int ST>
+__global__ __launch_bounds__(kThreads) void k_wide_fixup(Args a, const int* ovf) {
+  const int64_t id = blockIdx.x;
+  const int64_t xcd = id % 8, y = id / 8;
+  const int t = (int)(y % a.ntiles);
+  const int64_t b = (y / a.ntiles) * 8 + xcd;
+  if (b >= a.nblocks || !ovf[b]) return;
+  const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
+  wide_f64_block<ST>(a, a.rec + b * rec_words(a.p), r0, r1, a.tiles[t].x, a.tiles[t].y);
+}
+
 }  // namespace wide
 
 void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s) {
@@ -236,6 +249,13 @@ void launch_wide(const wide::Args& a, int st, int mode, hipStream_t s) {
   }
   if (st == 32) hipLaunchKernelGGL(wide::k_wide_f64<32>, grid, block, 0, s, a);
   else hipLaunchKernelGGL(wide::k_wide_f64<64>, grid, block, 0, s, a);
+}
+
+void launch_wide_fixup(const wide::Args& a, int st, const int* ovf, hipStream_t s) {
+  const int64_t nb8 = (a.nblocks + 7) / 8 * 8;
+  const dim3 grid((unsigned)(nb8 * a.ntiles)), block(wide::kThreads);
+  if (st == 32) hipLaunchKernelGGL(wide::k_wide_fixup<32>, grid, block, 0, s, a, ovf);
+  else hipLaunchKernelGGL(wide::k_wide_fixup<64>, grid, block, 0, s, a, ovf);
 }
 
 void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s) {

@@ -48,11 +48,11 @@ struct SegArgs {
   int64_t total_rows = 0;             //   min((k + 1) tile_rows, total_rows))
 };
 
-// FP32 matrix on BF16 matrix cores (wide_syrk.hip): F vector columns at
+// FP32 matrix on the int8 matrix cores (wide_syrk.hip): F vector columns at
 // consecutive 4-byte offsets of one plane, up to kSyrkMaxExtra other columns.
 constexpr int kSyrkGroup = 128;
 constexpr int kSyrkMaxExtra = 2;
-constexpr int kSyrkMaxPairs = 36;  // F <= 1024: at most 8 groups
+constexpr int kSyrkMaxPairs = 72;  // F <= 1024: at most 8 groups; every pair in two halves
 
 struct SyrkExtra {
   const char* base;  // element of row 0 of the launch
@@ -70,17 +70,21 @@ struct SyrkArgs {
   int ne;                   // extra columns, slots F..F+ne-1
   SyrkExtra ex[kSyrkMaxExtra];
   int npairs;
-  int2 pairs[kSyrkMaxPairs];  // (A, B) group pairs, A <= B
+  int2 pairs[kSyrkMaxPairs];  // (A + 16 half, B): group pairs A <= B, each in two halves
   int p;                    // F + ne
   const int32_t* col_of;    // user column of each slot (device)
   int64_t nblocks, nrows, R;  // R: rows per block (multiple of 64)
   uint64_t* rec;
   DevStatus* status;
+  int* ovf;                 // per block: nonzero = recompute in FP64 (device)
 };
 
 }  // namespace wide
 
 void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s);
+// FP64 records again for the blocks whose ovf flag is set (a.rec, a.R, a.nrows,
+// a.nblocks as for the launch that set them).
+void launch_wide_fixup(const wide::Args& a, int st, const int* ovf, hipStream_t s);
 
 // Persistent segmented launch (zeroes the queue first): nwg workgroups.
 void launch_seg(const wide::Args& a, const wide::SegArgs& g, int st, int nwg, hipStream_t s);

@@ -1,5 +1,5 @@
 // Host side of the wide-table path: slot table, super-tile list, launch
-// splitting and the choice between FP64 and split-BF16 matrix-core modes.
+// splitting and the choice between FP64 and split-precision matrix-core modes.
 #include <algorithm>
 #include <cstring>
 #include <vector>
@@ -10,19 +10,16 @@
 
 namespace st {
 
-// Split BF16 is used when asked for, or by default (PREC_AUTO) when every
-// column is stored as FP32 or int32 (FP32 values have 24 significant bits and
-// shifted int32 values below 2^26 pass the exactness guard, so the three
-// 9-bit digits hold them exactly within a block's range); otherwise FP64.
+// Split precision is used when asked for; by default (PREC_AUTO) only where
+// the int8 kernel takes the layout (syrk_layout below), whose blocks are
+// either on their sampled grid or recomputed in FP64.  The general split
+// kernel keeps 2^-27 of each block's range per element, which one outlier
+// widens for its whole block, so PREC_AUTO sends the other layouts to FP64.
 static int wide_mode(const stats_ctx* h) {
-  if (h->precision == STATS_PREC_FP64) return wide::MODE_FP64;
-  if (h->precision == STATS_PREC_SPLIT_BF16) return wide::MODE_SPLIT;
-  for (const auto& c : h->cols)
-    if (c.dtype != STATS_F32 && c.dtype != STATS_I32) return wide::MODE_FP64;
-  return wide::MODE_SPLIT;
+  return h->precision == STATS_PREC_FP64 ? wide::MODE_FP64 : wide::MODE_SPLIT;
 }
 
-// Layout test for the BF16 matrix-core kernel (wide_syrk.hip): F FP32
+// Layout test for the int8 matrix-core kernel (wide_syrk.hip): F FP32
 // columns (not flagged INTEGER) at byte offsets 0, 4, ..., 4 (F - 1) of one
 // plane with 16-byte aligned rows, F a multiple of 4, and at most
 // kSyrkMaxExtra other columns.  col_of receives the user column of each slot.
@@ -81,15 +78,34 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
   const int p = h->p;
   const int ne = p - F;
   const int ng = (F + wide::kSyrkGroup - 1) / wide::kSyrkGroup;
-  const int64_t R = wide_block_rows(h, nrows);
+  // the int32 digit sums are exact up to 32768 rows per block
+  const int64_t R = std::min<int64_t>(wide_block_rows(h, nrows), 32768);
   const int64_t W = rec_words(p);
   // records of one launch stay below ~1 GB
   const int64_t max_blocks = std::max<int64_t>(1, ((int64_t)1 << 30) / (W * 8));
-  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, sizeof(int32_t) * (size_t)p);
+  // FP64 super-tiles of the blocks that are computed again (launch_wide_fixup)
+  const int ST = p <= 32 ? 32 : 64;
+  const int fng = (p + ST - 1) / ST;
+  std::vector<int2> tiles;
+  for (int A = 0; A < fng; ++A)
+    for (int B = A; B < fng; ++B) tiles.push_back(make_int2(A, B));
+  auto up = [](size_t n) { return (n + 255) / 256 * 256; };
+  const size_t col_bytes = up(sizeof(int32_t) * (size_t)p);
+  const size_t tile_bytes = up(sizeof(int2) * tiles.size());
+  const size_t slot_bytes = up(sizeof(wide::SlotInfo) * (size_t)p);
+  const int64_t nb_max = std::min<int64_t>(max_blocks, (nrows + R - 1) / R);
+  const size_t ovf_bytes = up(sizeof(int) * (size_t)nb_max);
+  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, col_bytes + tile_bytes + slot_bytes + ovf_bytes);
   if (rc) return rc;
-  int32_t* col_dev = (int32_t*)h->aux3_dev;
+  char* aux = (char*)h->aux3_dev;
+  int32_t* col_dev = (int32_t*)aux;
+  int2* tiles_dev = (int2*)(aux + col_bytes);
+  wide::SlotInfo* slots_dev = (wide::SlotInfo*)(aux + col_bytes + tile_bytes);
+  int* ovf_dev = (int*)(aux + col_bytes + tile_bytes + slot_bytes);
   hipError_t e = hipMemcpyAsync(col_dev, col_of.data(), sizeof(int32_t) * (size_t)p,
                                 hipMemcpyHostToDevice, h->stream);
+  if (e == hipSuccess)
+    e = hipMemcpyAsync(tiles_dev, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "uploading column map");
   wide::SyrkArgs a;
   memset(&a, 0, sizeof a);
@@ -99,10 +115,15 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
   a.col_of = col_dev;
   a.npairs = 0;
   for (int A = 0; A < ng; ++A)
-    for (int B = A; B < ng; ++B) a.pairs[a.npairs++] = make_int2(A, B);
+    for (int B = A; B < ng; ++B) {
+      a.pairs[a.npairs++] = make_int2(A, B);
+      a.pairs[a.npairs++] = make_int2(A + 16, B);
+    }
   a.xstride = h->row_stride[xplane];
   a.R = R;
   a.status = h->status_dev;
+  a.ovf = ovf_dev;
+  std::vector<wide::SlotInfo> slots(p);
   int64_t done = 0;
   while (done < nrows) {
     const int64_t rows = std::min(nrows - done, max_blocks * R);
@@ -117,11 +138,35 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
       ex.chk = (col.dtype == STATS_F32 || col.dtype == STATS_F64) && (col.flags & STATS_COL_INTEGER);
       ex.isint = h->intf[col_of[F + x]];
     }
+    for (int c = 0; c < p; ++c) {
+      const stats_column& col = h->cols[c];
+      wide::SlotInfo& sl = slots[c];
+      sl.stride = h->row_stride[col.plane];
+      sl.base = (const char*)planes[col.plane] + col.byte_offset + done * sl.stride;
+      sl.kind = col.dtype;
+      sl.chk = (col.dtype == STATS_F32 || col.dtype == STATS_F64) && (col.flags & STATS_COL_INTEGER);
+      sl.isint = h->intf[c];
+      sl.pad[0] = sl.pad[1] = 0;
+    }
+    // the previous launch has read the table before this copy is ordered after it
+    e = hipMemcpyAsync(slots_dev, slots.data(), sizeof(wide::SlotInfo) * (size_t)p, hipMemcpyHostToDevice,
+                       h->stream);
+    if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
     rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
     if (rc) return rc;
     a.rec = h->rec;
     a.nblocks = nblocks;
     a.nrows = rows;
+    wide::Args f;
+    f.slots = slots_dev;
+    f.p = p;
+    f.tiles = tiles_dev;
+    f.ntiles = (int)tiles.size();
+    f.nblocks = nblocks;
+    f.nrows = rows;
+    f.R = R;
+    f.rec = h->rec;
+    f.status = h->status_dev;
     {
       Timer t;
       t.begin(h, STATS_K_SYRK);
@@ -130,6 +175,9 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
     }
     e = hipGetLastError();
     if (e != hipSuccess) return hip_fail(h, e, "matrix-core kernel launch");
+    launch_wide_fixup(f, ST, ovf_dev, h->stream);
+    e = hipGetLastError();
+    if (e != hipSuccess) return hip_fail(h, e, "FP64 block launch");
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
@@ -155,7 +203,7 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
   }
   const int ST = p <= 32 ? 32 : 64;
   const int ng = (p + ST - 1) / ST;
-  const int mode = wide_mode(h);
+  const int mode = h->precision == STATS_PREC_SPLIT ? wide::MODE_SPLIT : wide::MODE_FP64;
   std::vector<int2> tiles;
   for (int A = 0; A < ng; ++A)
     for (int B = A; B < ng; ++B) tiles.push_back(make_int2(A, B));

@@ -1,121 +1,190 @@
-// Wide FP32 tables on BF16 matrix cores: X_b^T X_b from exact digit products.
+// Wide FP32 tables on the int8 matrix cores: X_b^T X_b from exact digit
+// products.
 //
 // Scope: the vector columns are F FP32 values at consecutive 4-byte offsets
-// of one row-major plane (16-byte aligned rows), plus up to two extra
-// columns of any type (an identifier, say).  Other layouts use the general
-// kernels of wide.hip / wide_split.hip.
+// of one row-major plane (16-byte aligned rows, F a multiple of 4), plus up
+// to two extra columns of any type (an identifier, say).  Other layouts use
+// the general kernels of wide.hip / wide_split.hip.
 //
 // Method (section "Numerical Considerations": per-block mean shifting and
-// hi/lo splitting of the operands to recover the accuracy of low-precision
-// matrix units).  Every value is shifted by the block's first row K.  For a
-// window of 64 rows and one column, E is chosen with |x - K| <= 2^E over the
-// window, and v = (x - K) 2^(8-E) (|v| <= 256) is cut into three signed
-// digits, each an integer of magnitude <= 256 and hence exact in BF16:
-//     v = s1 + s2 2^-9 + s3 2^-18 + r,   |r| <= 2^-19.
-// For columns a, b the window's cross product is then
-//     2^(E_a + E_b - 16) sum_l 2^(-9 l) L_l,   L_l = sum_{i+j=l} sum_rows s_i s'_j,
-// nine BF16 products in five levels.  Each product is exact in FP32 and at most
-// 2^16; a level holds at most three products per row, so over 64 rows every
-// partial sum stays below 2^24 and the FP32 accumulation on the matrix cores
-// is exact.  Each window's levels are scaled and added into FP64.  The only
-// rounding is the dropped remainder r (2^-27 of the window's range): data
-// whose shifted values have at most 27 significant bits on that grid (FP32
-// values shifted within a few binades, integers below 2^26) give exact
-// window products.
+// splitting of the operands to recover the accuracy of low-precision matrix
+// units).  Every value is shifted by the block's first row K and put on a
+// binary grid of its column: v = rint((x - K) 2^s), an integer.  s is chosen
+// per block and column from 1024 rows spread over the block (its first and
+// last included) so that they need at most 21 bits, leaving a factor of two
+// to four of headroom below the limit |v| < 2^22.  v is cut into three signed byte
+// digits, exact in int8:
+//     v = d0 2^16 + d1 2^8 + d2,    d1, d2 in [-128, 127], |d0| <= 64.
+// The rounding and the digits take three vector operations per value:
+// y + 1.5 * 2^23 leaves rint(y) in the low mantissa bits, and one integer
+// add turns the bit pattern into v + 0x8080, whose bytes are d2 + 128,
+// d1 + 128 and d0; the bias of the two low bytes is removed on the packed
+// dwords (one XOR per four values).
+// For columns a, b the block's cross product is
+//     sum_rows v_a v_b = sum_l 2^(32 - 8 l) L_l,   L_l = sum_{i+j=l} sum_rows d_i d'_j,
+// nine digit products in five levels on v_mfma_i32_32x32x32_i8, whose int32
+// accumulation is exact (|L_l| < 3 * 2^14 per row, 2^31 over 32768 rows);
+// the levels are combined and scaled by 2^(-s_a - s_b) in FP64 once per
+// block.  The only rounding before FP64 is the grid: FP32 values within a
+// few binades of the shift (and integers below 2^21) lie on it, so their
+// products are exact.
+//
+// A block with a value beyond its column's limit, or a non-finite value, is
+// flagged (ovf[b]) by the diagonal pair that owns the column (every column
+// belongs to one); the FP64 matrix-core routine of wide.hip then computes
+// that block's whole record again (launch_wide_fixup), so every block is
+// either exact on its grid or FP64.
 //
 // Work split: vector columns form groups of 128.  A workgroup owns one block
-// of rows and one pair of groups (A, B), A <= B, and computes that 128 x 128
-// part of Q with 32 x 32 x 16 BF16 MFMAs; the diagonal pair (A, A) also sums
-// its columns (S), writes their shifts, and forms their products with the
-// extra columns in FP64 on the vector units.  Staged columns sit in LDS in a
-// permuted order that keeps both the digit writes and the operand reads free
-// of bank conflicts.  Workgroup ids put all pairs of
-// one block on the same XCD (ids congruent modulo 8), so the block's rows are
-// fetched from HBM once and re-read from that XCD's L2.
+// of rows and one half of a pair of groups (A, B), A <= B: two tile rows of
+// A for an off-diagonal pair (8 tiles), tile rows {0, 3} or {1, 2} of a
+// diagonal one (5 upper tiles).  Eight waves, two per SIMD, with one 32 x 32
+// tile each (its five int32 levels in 80 accumulation registers), so that
+// each wave's waits are covered by the other wave of its SIMD;
+// half 0 of a diagonal pair also sums its columns and forms their products
+// with the extra columns in FP64 on the vector units.  Workgroup ids put all
+// pairs of one block on the same XCD (ids congruent modulo 8), so the block's
+// rows come from HBM once and from that XCD's L2 after.
 //
-// Per window: each wave-instruction loads 16 bytes per lane, i.e. one row's
-// 256 columns of the pair (off-diagonal) or two rows' 128 (diagonal), fully
-// coalesced; the next window's loads are issued as soon as the current one is
-// converted, so they overlap the matrix-core phase.
+// Data path per 32-row sub-step: each wave moves its own four rows (and
+// their extra-column values) from HBM into an LDS ring of three stages by
+// direct DMA (global_load_lds, two sub-steps in flight) and converts exactly
+// those rows, so its only wait on the ring is its own vector-memory counter.
+// The digits go to a double-buffered LDS array, [digit][4-row group][column]
+// as dwords of four rows; one barrier per sub-step separates the conversion
+// of sub-step t + 1 from the products of sub-step t.  The K index of a
+// product is the row, so a lane's operand dwords j = 0..3 are its column's
+// row groups 4h + j.  The conversion of sub-step t + 1 and the products of
+// sub-step t are independent, so the compiler interleaves the vector work
+// into the matrix-core shadow.
+#include <type_traits>
+
 #include "common.hpp"
 #include "wide.hpp"
 
 namespace st {
 namespace syrk {
 
-typedef float f16v __attribute__((ext_vector_type(16)));
-typedef __bf16 bf8 __attribute__((ext_vector_type(8)));
-typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef int i4 __attribute__((ext_vector_type(4)));
+typedef int i16 __attribute__((ext_vector_type(16)));
 typedef float fl4 __attribute__((ext_vector_type(4)));
+typedef float fl2 __attribute__((ext_vector_type(2)));
+typedef unsigned int u4 __attribute__((ext_vector_type(4)));
+typedef unsigned int u2 __attribute__((ext_vector_type(2)));
 
-constexpr int kThreads = 256;
+constexpr int kThreads = 512;
+constexpr int NW = kThreads / 64;    // waves
+constexpr int RW = 32 / NW;          // rows per wave per sub-step
+constexpr int MT = 1;                // tiles per wave
 constexpr int G = wide::kSyrkGroup;  // vector columns per group
-constexpr int WR = 64;               // rows per window
-constexpr int DS = WR + 8;           // LDS bf16 per staged column (rows contiguous, padded)
-constexpr int MAXT = 4;              // 32 x 32 tiles per wave
+constexpr int SR = 32;               // rows per sub-step (K of one product)
+constexpr int NST = 3;               // stages in the LDS ring
+constexpr int RAWB = SR * 2 * G * 4; // row bytes per stage (32 rows x 256 FP32)
+constexpr int EXW = 4 * RW;          // extra-column dwords per wave per stage
+constexpr int STB = RAWB + 8 * EXW * 4;  // stage bytes: rows, then the waves' extras
+constexpr int PITCH_MAX = 2 * G + 8;
+constexpr int NSAMP = 1024;          // rows sampled per block for the grids
+constexpr int SB = 16;               // sampled rows per wave in flight
+constexpr float kVlim = 4194303.0f;  // |v| < 2^22: the rounding constant below holds v exactly
+constexpr float kRound = 12582912.0f; // 1.5 * 2^23: y + kRound is rint(y) in the low mantissa bits
+constexpr int kBias = 0x8080 - 0x4B400000;  // bits(y + kRound) + kBias = v + 0x8080
+constexpr int NE = wide::kSyrkMaxExtra;
+static_assert(NE <= 2 && RW == 4, "extras: two columns of two dwords in four rows per wave");
 
-// Upper 32 x 32 tiles (i, j) of a diagonal pair, dealt to waves round-robin.
-__device__ inline void diag_tile(int k, int& i, int& j) {
-  switch (k) {
-    case 0: i = 0; j = 0; break;
-    case 1: i = 0; j = 1; break;
-    case 2: i = 0; j = 2; break;
-    case 3: i = 0; j = 3; break;
-    case 4: i = 1; j = 1; break;
-    case 5: i = 1; j = 2; break;
-    case 6: i = 1; j = 3; break;
-    case 7: i = 2; j = 2; break;
-    case 8: i = 2; j = 3; break;
-    default: i = 3; j = 3; break;
-  }
-}
-
-// LDS position of staged column s: a rotation within each group of four, so
-// that both access patterns are free of bank conflicts with the odd 16-byte
-// column pitch: the conversion (lane q writes column 4q + i) and the operand
-// reads (lane q reads column 32t + q).
-__device__ inline int lpos(int s) { return (s & ~3) | ((s + (s >> 4)) & 3); }
-
-// Tile u of wave w (off-diagonal: the wave's tiles share one tile column).
-template <bool DIAG>
-__device__ inline void wave_tile(int u, int w, int& i, int& j) {
-  if (DIAG) {
-    diag_tile(4 * u + w, i, j);
-  } else {
-    i = u;
-    j = w;
-  }
-}
-
-struct Smem {
-  unsigned short dig[3][2 * G][DS];  // digits, [digit][LDS column position][row]
-  float mx[8][2 * G];                // per row group: window max / min of x
-  float mn[8][2 * G];
-  double pw[2 * G];                  // 2^(E - 8) of the window
-  double sc[2 * G];                  // 2^(8 - E)
-  double K[2 * G];                   // shifts of the staged columns
-  double red[8][G];                  // row-group partials (diagonal pair)
+// s_waitcnt immediate: at most N vector-memory loads of this wave outstanding.
+template <int N>
+struct VmWait {
+  static constexpr int imm = (N & 15) | (7 << 4) | (15 << 8) | (((N >> 4) & 3) << 14);
 };
 
-// Extra column value in row r as FP64, shifted (int64 through Ki).
-__device__ inline double extra_value(const wide::SyrkExtra& e, int64_t r, double K, int64_t Ki,
-                                     uint32_t& bad) {
-  const char* p = e.base + r * e.stride;
-  switch (e.kind) {
-    case STATS_I32: return (double)*(const int32_t*)p - K;
-    case STATS_I64: return (double)(*(const int64_t*)p - Ki);
-    case STATS_F32: {
-      const double x = (double)*(const float*)p;
-      if (e.chk) bad |= (x != __builtin_rint(x));
-      return x - K;
-    }
-    default: {
-      const double x = *(const double*)p;
-      if (e.chk) bad |= (x != __builtin_rint(x));
-      return x - K;
-    }
+// Shapes of the two workgroup kinds.
+template <bool DIAG>
+struct Shape {
+  static constexpr int NC = DIAG ? G : 2 * G;  // staged columns
+  static constexpr int CPL = NC / 64;           // columns converted per lane
+  static constexpr int PITCH = NC + 8;          // dwords per 4-row group (4 PITCH = 32 mod 64 banks)
+  static constexpr int RB = NC * 4;             // bytes per staged row
+  static constexpr int NROW = DIAG ? RW / 2 : RW;  // row DMA instructions per wave per sub-step
+};
+
+// Tiles (ti, tj) of a wave, at most MT; off-diagonal pairs: tile row w.
+struct WaveTiles {
+  int n;
+  int ti[MT], tj[MT];
+};
+
+template <bool DIAG>
+__device__ inline WaveTiles wave_tiles(int w, int half) {
+  WaveTiles r;
+  if (!DIAG) {
+    // tile row 2 half + w / 4 of A, tile column w % 4 of B
+    r.n = 1;
+    r.ti[0] = 2 * half + (w >> 2);
+    r.tj[0] = w & 3;
+    return r;
   }
+  // a diagonal half: the upper tiles of tile rows {0, 3} (half 0) or {1, 2}
+  // (half 1) of the 4 x 4 tiles, one per wave; waves without a tile run the
+  // same product code on a dummy one
+  switch (half * 8 + w) {
+    case 0: r.n = 1; r.ti[0] = 0; r.tj[0] = 0; break;
+    case 1: r.n = 1; r.ti[0] = 0; r.tj[0] = 1; break;
+    case 2: r.n = 1; r.ti[0] = 0; r.tj[0] = 2; break;
+    case 3: r.n = 1; r.ti[0] = 0; r.tj[0] = 3; break;
+    case 4: r.n = 1; r.ti[0] = 3; r.tj[0] = 3; break;
+    case 8: r.n = 1; r.ti[0] = 1; r.tj[0] = 1; break;
+    case 9: r.n = 1; r.ti[0] = 1; r.tj[0] = 2; break;
+    case 10: r.n = 1; r.ti[0] = 1; r.tj[0] = 3; break;
+    case 11: r.n = 1; r.ti[0] = 2; r.tj[0] = 2; break;
+    case 12: r.n = 1; r.ti[0] = 2; r.tj[0] = 3; break;
+    default: r.n = 0; r.ti[0] = 0; r.tj[0] = 0; break;
+  }
+  return r;
 }
+
+// LDS reads of the DMA target, each in one asm block with its own completion
+// wait: the compiler would otherwise make them wait for every DMA in flight.
+template <int RBYTES>
+__device__ inline void raw_read4(uint32_t a, fl4 (&x)[4]) {
+  static_assert(RBYTES == 1024, "off-diagonal rows");
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %4 offset:1024\n\t"
+      "ds_read_b128 %2, %4 offset:2048\n\t"
+      "ds_read_b128 %3, %4 offset:3072\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+      : "v"(a));
+}
+
+__device__ inline void raw_read2(uint32_t a, fl2 (&x)[4]) {
+  asm volatile(
+      "ds_read_b64 %0, %4\n\t"
+      "ds_read_b64 %1, %4 offset:512\n\t"
+      "ds_read_b64 %2, %4 offset:1024\n\t"
+      "ds_read_b64 %3, %4 offset:1536\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+      : "v"(a));
+}
+
+// extras of four rows: x[2e] low dwords, x[2e + 1] high dwords of extra e
+__device__ inline void ex_read(uint32_t a, u4 (&x)[4]) {
+  asm volatile(
+      "ds_read_b128 %0, %4\n\t"
+      "ds_read_b128 %1, %4 offset:16\n\t"
+      "ds_read_b128 %2, %4 offset:32\n\t"
+      "ds_read_b128 %3, %4 offset:48\n\t"
+      "s_waitcnt lgkmcnt(0)"
+      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
+      : "v"(a));
+}
+
+// Barrier after this wave's LDS writes, without waiting for the DMA loads in
+// flight (a __syncthreads() fence would wait for them too).
+__device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
+
+__device__ inline bool wide_kind(int kind) { return kind == STATS_I64 || kind == STATS_F64; }
 
 __device__ inline void extra_shift(const wide::SyrkExtra& e, int64_t r0, double& K, int64_t& Ki) {
   const char* p = e.base + r0 * e.stride;
@@ -134,322 +203,689 @@ __device__ inline uint64_t shift_word(bool isint, int kind, double K, int64_t Ki
   return (fabs(K) < 4.0e18) ? (uint64_t)(int64_t)K : (uint64_t)0x7FFFFFFFFFFFFFFFll;
 }
 
-// Two BF16 digits (integers |s| <= 256, exact) packed low = row 2m, high = row 2m+1.
-__device__ inline uint32_t pack_bf16(double lo, double hi) {
-  return __builtin_amdgcn_perm(__float_as_uint((float)hi), __float_as_uint((float)lo), 0x07060302u);
+// Grid exponent s of a column whose sampled shifted values reach m
+// (m < 2^e): s = 21 - e.  With m = 0 the grid is the spacing of FP32 values
+// in K's binade, or 1 for K = 0.  Clamped so that 2^s is a normal FP32
+// number.
+__device__ inline int grid_exp(double m, float K) {
+  int e = 0;
+  int s;
+  if (m > 0.0) {
+    (void)frexp(m, &e);
+    s = 21 - e;
+  } else if (K != 0.0f) {
+    (void)frexp((double)K, &e);
+    s = 23 - e;
+  } else {
+    s = 0;
+  }
+  return max(-126, min(127, s));
 }
 
-// One block of rows and one pair of column groups (A, B).
-template <bool DIAG>
-__device__ void pair_block(const wide::SyrkArgs& a, Smem& sm, int64_t b, int A, int B) {
-  constexpr int NR = DIAG ? 8 : 16;  // rows per lane per window
-  const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
-  const int lane = threadIdx.x & 63, h = lane >> 5, q = lane & 31;
-  const int wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
-  const int grp = DIAG ? A : (h ? B : A);
-  const int sl0 = (DIAG ? 0 : h * G) + 4 * q;
-  const int c0 = grp * G + 4 * q;
-  const bool colv = c0 < a.F;
-  const int rb = DIAG ? 16 * wave + 8 * h : 16 * wave;
-  const int rg = DIAG ? 2 * wave + h : wave;
-  constexpr int NRG = DIAG ? 8 : 4;
-  constexpr int NSL = DIAG ? G : 2 * G;
-  const int ne = a.ne;
-  const int boff = DIAG ? 0 : G;
-  const int nt = DIAG ? (wave < 2 ? 3 : 2) : 4;
-  const char* xrow0 = a.xbase + 4 * (int64_t)c0;
-  fl4 Kf = (fl4){0.f, 0.f, 0.f, 0.f};
-  if (colv) Kf = *(const fl4*)(xrow0 + r0 * a.xstride);
-  double Kd[4];
+// One sub-step's per-lane sums, added into the running sums after the barrier.
+template <int CPL>
+struct Pending {
+  int is[CPL];         // sum of the lane's v per column (|sum| < 2^26)
+  double sp[NE][CPL];  // sum of v * (extra - K_e) per column
+  double es[NE];       // extras: sums and products of the wave's rows
+  double eq[NE * (NE + 1) / 2];
+};
+
+// DIAG: a diagonal half; SUMS: it also forms the column sums, the products
+// with the extra columns and the checks of the block (half 0 of a diagonal
+// pair: every column of the table is in exactly one such workgroup).
+template <bool DIAG, bool SUMS>
+struct Ctx {
+  static constexpr int NC = Shape<DIAG>::NC;
+  static constexpr int CPL = Shape<DIAG>::CPL;
+  static constexpr int PITCH = Shape<DIAG>::PITCH;
+  static constexpr int RB = Shape<DIAG>::RB;
+  const wide::SyrkArgs& a;
+  unsigned char* ring;  // LDS stages (DMA target only)
+  int* dig;             // LDS digits [2][3][8][PITCH]
+  const float* s_sc;    // 2^s per staged column (0: not converted)
+  const float* s_nks;   // -K 2^s
+  const double* s_eK;   // shifts of the extra columns
+  const int64_t* s_eKi;
+  int64_t r0, r1;
+  int A, B, lane, wave, h, q, ne;
+  int cl0;              // first staged column converted by this lane
+  bool over;            // a value left its grid or was not finite
+  uint32_t bad;
+
+  __device__ Ctx(const wide::SyrkArgs& a_) : a(a_) {}
+
+  // global vector column of staged column c
+  __device__ __attribute__((always_inline)) int gcol(int c) const { return DIAG ? A * G + c : (c < G ? A * G + c : B * G + (c - G)); }
+
+  // DMA of this wave's rows of sub-step t (and their extra values) into
+  // stage t % NST: a fixed number of instructions, every lane active on the
+  // row loads (rows past the block end read its last row, columns past F
+  // read column 0; both are ignored).
+  __device__ __attribute__((always_inline)) void issue(int64_t t) const {
+    const int64_t rb = r0 + t * SR + RW * wave;
+    unsigned char* stage = ring + (int)(t % NST) * STB;  // prologue and last sub-steps only
+    unsigned char* dst = stage + RW * wave * RB;
+    if constexpr (DIAG) {
+      const int dc = A * G + 4 * (lane & 31);
+      const int64_t col = dc < a.F ? dc : 0;
 #pragma unroll
-  for (int i = 0; i < 4; ++i) Kd[i] = (double)Kf[i];
-  if (rg == 0) {
+      for (int m = 0; m < RW / 2; ++m) {
+        int64_t r = rb + 2 * m + h;
+        r = r < r1 ? r : r1 - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * col),
+                                         (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
+      }
+      if (ne > 0) {
+        // lane 8e + 4w + j: dword w of extra e in row j (lanes >= 16 idle)
+        const int e = lane >> 3, wd = (lane >> 2) & 1, j = lane & 3;
+        if (lane < 16 && e < ne && (wd == 0 || wide_kind(a.ex[e].kind))) {
+          int64_t r = rb + j;
+          r = r < r1 ? r : r1 - 1;
+          __builtin_amdgcn_global_load_lds((const void*)(a.ex[e].base + r * a.ex[e].stride + 4 * wd),
+                                           (__attribute__((address_space(3))) void*)(stage + RAWB + wave * EXW * 4),
+                                           4, 0, 0);
+        }
+      }
+    } else {
+      const int dc = gcol(4 * lane);
+      const int64_t col = dc < a.F ? dc : 0;
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sm.K[sl0 + i] = Kd[i];
-  }
-  double eK[wide::kSyrkMaxExtra];
-  int64_t eKi[wide::kSyrkMaxExtra];
-#pragma unroll
-  for (int e = 0; e < wide::kSyrkMaxExtra; ++e) {
-    eK[e] = 0.0;
-    eKi[e] = 0;
-    if (DIAG && e < ne) extra_shift(a.ex[e], r0, eK[e], eKi[e]);
-  }
-  double Q[MAXT][16];
-#pragma unroll
-  for (int u = 0; u < MAXT; ++u)
-#pragma unroll
-    for (int k = 0; k < 16; ++k) Q[u][k] = 0.0;
-  double S[4] = {0.0, 0.0, 0.0, 0.0};
-  double strip[wide::kSyrkMaxExtra][4];
-#pragma unroll
-  for (int e = 0; e < wide::kSyrkMaxExtra; ++e)
-#pragma unroll
-    for (int i = 0; i < 4; ++i) strip[e][i] = 0.0;
-  const bool self = DIAG && A == 0 && q == 0;
-  double eS[wide::kSyrkMaxExtra] = {};
-  double eQ[wide::kSyrkMaxExtra * (wide::kSyrkMaxExtra + 1) / 2] = {};
-  uint32_t bad = 0;
-  fl4 raw[NR];
-  auto load_window = [&](int64_t w0) {
-#pragma unroll
-    for (int j = 0; j < NR; ++j) {
-      const int64_t r = w0 + rb + j;
-      raw[j] = Kf;
-      if (colv && r < r1) raw[j] = __builtin_nontemporal_load((const fl4*)(xrow0 + r * a.xstride));
+      for (int j = 0; j < RW; ++j) {
+        int64_t r = rb + j;
+        r = r < r1 ? r : r1 - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * col),
+                                         (__attribute__((address_space(3))) void*)(dst + j * RB), 16, 0, 0);
+      }
     }
+  }
+
+  // The same DMA for a sub-step that lies inside the block: the lane's row
+  // pointers are advanced by the caller (rp: this wave's first row of the
+  // sub-step, at the lane's column; ep: the lane's extra element), no clamps.
+  __device__ __attribute__((always_inline)) void issue_inside(int stage_i, const char* rp, const char* ep) const {
+    unsigned char* stage = ring + stage_i * STB;
+    unsigned char* dst = stage + RW * wave * RB;
+    if constexpr (DIAG) {
+#pragma unroll
+      for (int m = 0; m < RW / 2; ++m)
+        __builtin_amdgcn_global_load_lds((const void*)(rp + 2 * m * a.xstride),
+                                         (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
+      if (ne > 0) {
+        const int e = lane >> 3, wd = (lane >> 2) & 1;
+        if (lane < 16 && e < ne && (wd == 0 || wide_kind(a.ex[e].kind)))
+          __builtin_amdgcn_global_load_lds((const void*)ep,
+                                           (__attribute__((address_space(3))) void*)(stage + RAWB + wave * EXW * 4),
+                                           4, 0, 0);
+      }
+    } else {
+#pragma unroll
+      for (int j = 0; j < RW; ++j)
+        __builtin_amdgcn_global_load_lds((const void*)(rp + j * a.xstride),
+                                         (__attribute__((address_space(3))) void*)(dst + j * RB), 16, 0, 0);
+    }
+  }
+
+  // waits until the DMA of the oldest sub-step in flight has landed, with
+  // LATER (0, 1, 2) sub-steps issued after it
+  template <int LATER>
+  __device__ __attribute__((always_inline)) void wait_dma() const {
+    constexpr int n = Shape<DIAG>::NROW;
+    if (DIAG && ne > 0) __builtin_amdgcn_s_waitcnt(VmWait<LATER * (n + 1)>::imm);
+    else __builtin_amdgcn_s_waitcnt(VmWait<LATER * n>::imm);
+  }
+
+  __device__ __attribute__((always_inline)) uint32_t lds(const void* p) const { return (uint32_t)(uintptr_t)p; }
+
+  // Raw values of one sub-step for this lane: CPL columns x RW rows.
+  struct Raw {
+    float x[RW][CPL];
   };
-  load_window(r0);
-  __syncthreads();  // shifts in LDS
-  for (int64_t w0 = r0; w0 < r1; w0 += WR) {
-    // ---- window range per column -> grid exponent E ----
-    fl4 mx = raw[0], mn = raw[0];
+
+  // LDS reads of stage t (its DMA has landed)
+  __device__ __attribute__((always_inline)) void fetch(int stage_i, Raw& r) const {
+    const uint32_t st = lds(ring) + (uint32_t)(stage_i * STB);
 #pragma unroll
-    for (int j = 1; j < NR; ++j) {
+    for (int g = 0; g < RW / 4; ++g) {
+      const uint32_t ad = st + (uint32_t)((RW * wave + 4 * g) * RB + 4 * cl0);
+      if constexpr (DIAG) {
+        fl2 v[4];
+        raw_read2(ad, v);
 #pragma unroll
-      for (int i = 0; i < 4; ++i) {
-        mx[i] = fmaxf(mx[i], raw[j][i]);
-        mn[i] = fminf(mn[i], raw[j][i]);
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) r.x[4 * g + j][i] = v[j][i];
+      } else {
+        fl4 v[4];
+        raw_read4<RB>(ad, v);
+#pragma unroll
+        for (int j = 0; j < 4; ++j)
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) r.x[4 * g + j][i] = v[j][i];
       }
     }
-    *(fl4*)&sm.mx[rg][sl0] = mx;
-    *(fl4*)&sm.mn[rg][sl0] = mn;
-    __syncthreads();  // also: the previous window's digit reads are over
-    for (int s = threadIdx.x; s < NSL; s += kThreads) {
-      float M = sm.mx[0][s], m = sm.mn[0][s];
-#pragma unroll
-      for (int g = 1; g < NRG; ++g) {
-        M = fmaxf(M, sm.mx[g][s]);
-        m = fminf(m, sm.mn[g][s]);
+  }
+
+  // extra e's shifted value in row j (0..3) of a group of fetched dwords
+  __device__ __attribute__((always_inline)) double extra_of(const u4 (&w)[4], int e, int j) {
+    const uint32_t lo = w[2 * e][j], hi = w[2 * e + 1][j];
+    const wide::SyrkExtra& x = a.ex[e];
+    switch (x.kind) {
+      case STATS_I32: return (double)(int32_t)lo - s_eK[e];
+      case STATS_I64: return (double)((int64_t)(((uint64_t)hi << 32) | lo) - s_eKi[e]);
+      case STATS_F32: {
+        const double y = (double)__uint_as_float(lo);
+        if (x.chk) bad |= (y != __builtin_rint(y));
+        return y - s_eK[e];
       }
-      const double k = sm.K[s];
-      const double dm = fmax((double)M - k, k - (double)m);
-      int E = 0;
-      if (dm > 0.0) (void)frexp(dm, &E);  // dm < 2^E
-      sm.pw[s] = ldexp(1.0, E - 8);
-      sm.sc[s] = ldexp(1.0, 8 - E);
+      default: {
+        const double y = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+        if (x.chk) bad |= (y != __builtin_rint(y));
+        return y - s_eK[e];
+      }
     }
-    __syncthreads();
-    // ---- digits (and, on the diagonal pair, column sums and extra strips) ----
-    double sc[4], pw[4], nKs[4];
+  }
+
+  // Digits of sub-step t into digit buffer t & 1; with SUMS also the sums
+  // of v, its products with the extras and the checks of limit and
+  // finiteness.
+  template <bool TAIL>
+  __device__ __attribute__((always_inline)) void digitize(int64_t t, int stage_i, Raw& r, Pending<CPL>& pd) {
+    float sc[CPL], nks[CPL], mx[CPL], fs[CPL];
+    int sw[CPL];
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      sc[i] = sm.sc[sl0 + i];
-      pw[i] = sm.pw[sl0 + i];
-      nKs[i] = -Kd[i] * sc[i];
-    }
-    double de[wide::kSyrkMaxExtra][NR];
-    if (DIAG) {
+    for (int i = 0; i < CPL; ++i) {
+      sc[i] = s_sc[cl0 + i];
+      nks[i] = s_nks[cl0 + i];
+      mx[i] = fs[i] = 0.0f;
+      sw[i] = 0;
 #pragma unroll
-      for (int e = 0; e < wide::kSyrkMaxExtra; ++e)
-#pragma unroll
-        for (int j = 0; j < NR; ++j) {
-          de[e][j] = 0.0;
-          const int64_t r = w0 + rb + j;
-          if (e < ne && r < r1) de[e][j] = extra_value(a.ex[e], r, eK[e], eKi[e], bad);
-        }
+      for (int e = 0; e < NE; ++e) pd.sp[e][i] = 0.0;
     }
 #pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      uint32_t pk[3][NR / 2];
-      double ws = 0.0;
-      double wstrip[wide::kSyrkMaxExtra] = {};
+    for (int e = 0; e < NE; ++e) pd.es[e] = 0.0;
 #pragma unroll
-      for (int j = 0; j < NR; j += 2) {
-        double s1[2], s2[2], s3[2];
+    for (int k = 0; k < NE * (NE + 1) / 2; ++k) pd.eq[k] = 0.0;
+    const int64_t rb = r0 + t * SR + RW * wave;
 #pragma unroll
-        for (int m = 0; m < 2; ++m) {
-          const double v = __builtin_fma((double)raw[j + m][i], sc[i], nKs[i]);  // (x - K) sc, exact
-          ws += v;
-          if (DIAG) {
+    for (int g = 0; g < RW / 4; ++g) {
+      uint32_t dw[3][CPL];
+      double de[4][NE];
+      if (SUMS && ne > 0) {
+        u4 ew[4];
+        ex_read(lds(ring) + (uint32_t)(stage_i * STB + RAWB + wave * EXW * 4 + 16 * g), ew);
 #pragma unroll
-            for (int e = 0; e < wide::kSyrkMaxExtra; ++e)
-              if (e < ne) wstrip[e] = __builtin_fma(v, de[e][j + m], wstrip[e]);
+        for (int jj = 0; jj < 4; ++jj) {
+          const bool live = !TAIL || rb + 4 * g + jj < r1;
+#pragma unroll
+          for (int e = 0; e < NE; ++e) de[jj][e] = (e < ne && live) ? extra_of(ew, e, jj) : 0.0;
+          if (A == 0 && lane == 0) {
+            int tq = 0;
+#pragma unroll
+            for (int e = 0; e < NE; ++e) {
+              pd.es[e] += de[jj][e];
+#pragma unroll
+              for (int f = e; f < NE; ++f, ++tq) pd.eq[tq] = __builtin_fma(de[jj][e], de[jj][f], pd.eq[tq]);
+            }
           }
-          s1[m] = __builtin_rint(v);
-          const double t1 = __builtin_fma(s1[m], -512.0, v * 512.0);  // (v - s1) 2^9, exact
-          s2[m] = __builtin_rint(t1);
-          s3[m] = __builtin_rint((t1 - s2[m]) * 512.0);
         }
-        pk[0][j / 2] = pack_bf16(s1[0], s1[1]);
-        pk[1][j / 2] = pack_bf16(s2[0], s2[1]);
-        pk[2][j / 2] = pack_bf16(s3[0], s3[1]);
-      }
-      S[i] = __builtin_fma(ws, pw[i], S[i]);
-      if (DIAG) {
-#pragma unroll
-        for (int e = 0; e < wide::kSyrkMaxExtra; ++e)
-          if (e < ne) strip[e][i] = __builtin_fma(wstrip[e], pw[i], strip[e][i]);
       }
 #pragma unroll
-      for (int d = 0; d < 3; ++d)
+      for (int i = 0; i < CPL; ++i) {
+        int w[4];
 #pragma unroll
-        for (int c = 0; c < NR / 8; ++c)
-          *(u4*)&sm.dig[d][lpos(sl0 + i)][rb + 8 * c] =
-              (u4){pk[d][4 * c], pk[d][4 * c + 1], pk[d][4 * c + 2], pk[d][4 * c + 3]};
+        for (int jj = 0; jj < 4; ++jj) {
+          float y = __builtin_fmaf(r.x[4 * g + jj][i], sc[i], nks[i]);
+          if (TAIL) y = (rb + 4 * g + jj < r1) ? y : 0.0f;
+          const float fr = y + kRound;
+          w[jj] = __float_as_int(fr) + kBias;  // v + 0x8080: bytes d2 + 128, d1 + 128, d0
+          if constexpr (SUMS) {
+            mx[i] = fmaxf(mx[i], fabsf(y));
+            fs[i] += y;  // NaN and infinity show here
+            sw[i] += w[jj];
+            if (ne > 0) {
+              const double v = (double)(fr - kRound);
+#pragma unroll
+              for (int e = 0; e < NE; ++e)
+                if (e < ne) pd.sp[e][i] = __builtin_fma(v, de[jj][e], pd.sp[e][i]);
+            }
+          }
+        }
+        // byte transpose: digit k of the four rows into one dword
+        const uint32_t p01 = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);
+        const uint32_t p23 = __builtin_amdgcn_perm(w[3], w[2], 0x05010400u);
+        const uint32_t q01 = __builtin_amdgcn_perm(w[1], w[0], 0x0C0C0602u);
+        const uint32_t q23 = __builtin_amdgcn_perm(w[3], w[2], 0x0C0C0602u);
+        dw[2][i] = __builtin_amdgcn_perm(p23, p01, 0x05040100u) ^ 0x80808080u;  // d2 (lowest)
+        dw[1][i] = __builtin_amdgcn_perm(p23, p01, 0x07060302u) ^ 0x80808080u;  // d1
+        dw[0][i] = __builtin_amdgcn_perm(q23, q01, 0x05040100u);                // d0 (highest)
+      }
+      int* out = dig + ((int)(t & 1) * 3 * 8 + (RW / 4) * wave + g) * PITCH + cl0;
+#pragma unroll
+      for (int d = 0; d < 3; ++d) {
+        if constexpr (CPL == 4) *(u4*)(out + d * 8 * PITCH) = (u4){dw[d][0], dw[d][1], dw[d][2], dw[d][3]};
+        else *(u2*)(out + d * 8 * PITCH) = (u2){dw[d][0], dw[d][1]};
+      }
+    }
+    if constexpr (SUMS) {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        over |= !(mx[i] <= kVlim) | !(fabsf(fs[i]) <= 3.0e38f);
+        pd.is[i] = sw[i] - RW * 0x8080;
+      }
+    }
+  }
+};
+
+// One operand: digit d of staged column c in rows 16h..16h+15 of buffer buf.
+template <bool DIAG>
+__device__ inline i4 operand(const int* base, int d, int c) {
+  constexpr int PITCH = Shape<DIAG>::PITCH;
+  i4 r;
+#pragma unroll
+  for (int j = 0; j < 4; ++j) r[j] = base[(d * 8 + j) * PITCH + c];
+  return r;
+}
+
+// Products of one sub-step's digits (buffer buf) into the wave's tiles
+// (2 on an off-diagonal half, 3 on a diagonal pair; tiles past the last
+// vector column multiply zero digits and are not written): digit d of the
+// B operand meets the three digits of A in levels d..d+2; consecutive
+// products go to different tiles.
+template <bool DIAG>
+__device__ inline void mma_step(const int* dig, int buf, const WaveTiles& wt, int h, int q, i16 (&L)[MT][5]) {
+  constexpr int PITCH = Shape<DIAG>::PITCH;
+  constexpr int NT = MT;
+  const int* base = dig + (buf * 3 * 8 + 4 * h) * PITCH + q;
+  constexpr int boff = DIAG ? 0 : G;
+  // all of a wave's tiles are in one tile row: one A operand
+  i4 fa[3];
+#pragma unroll
+  for (int d = 0; d < 3; ++d) fa[d] = operand<DIAG>(base, d, 32 * wt.ti[0]);
+#pragma unroll
+  for (int d = 0; d < 3; ++d) {
+    i4 fb[NT];
+#pragma unroll
+    for (int u = 0; u < NT; ++u) fb[u] = operand<DIAG>(base, d, boff + 32 * wt.tj[u]);
+#pragma unroll
+    for (int k = 0; k < 3; ++k)
+#pragma unroll
+      for (int u = 0; u < NT; ++u)
+        L[u][d + k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[k], fb[u], L[u][d + k], 0, 0, 0);
+  }
+}
+
+struct Lds {
+  unsigned char* ring;
+  int* dig;
+  double* red;      // [NW][256], shares memory with dig
+  int* s_exp;
+  float* s_K;
+  float* s_sc;
+  float* s_nks;
+  double* s_eK;
+  int64_t* s_eKi;
+  double* s_ex;     // [NW][8]: extras' per-wave sums and products
+};
+
+// One block of rows and one pair of column groups (A, B).
+template <bool DIAG, bool SUMS>
+__device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& a, const Lds& m, int64_t b, int A,
+                                                         int B, int half) {
+  constexpr int NC = Shape<DIAG>::NC;
+  constexpr int CPL = Shape<DIAG>::CPL;
+  Ctx<DIAG, SUMS> c(a);
+  c.ring = m.ring;
+  c.dig = m.dig;
+  c.s_sc = m.s_sc;
+  c.s_nks = m.s_nks;
+  c.s_eK = m.s_eK;
+  c.s_eKi = m.s_eKi;
+  c.r0 = b * a.R;
+  c.r1 = min(c.r0 + a.R, a.nrows);
+  c.A = A;
+  c.B = B;
+  c.lane = threadIdx.x & 63;
+  c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
+  c.h = c.lane >> 5;
+  c.q = c.lane & 31;
+  c.ne = SUMS ? a.ne : 0;
+  c.cl0 = CPL * c.lane;
+  c.over = false;
+  c.bad = 0;
+  const bool colv = c.gcol(c.cl0) < a.F;
+  const int64_t nrow = c.r1 - c.r0;
+  const int64_t nsub = (nrow + SR - 1) / SR;
+  const int tid = threadIdx.x;
+  uint64_t* out = a.rec + b * rec_words(a.p);
+  const bool self = SUMS && A == 0 && c.ne > 0 && c.lane == 0;
+
+  c.issue(0);
+  if (nsub > 1) c.issue(1);
+  if (nsub > 2) c.issue(2);
+  // ---- shifts; grids from NSAMP rows spread over the block ----
+  for (int k = tid; k < NC; k += kThreads) {
+    const int g = c.gcol(k);
+    m.s_K[k] = *(const float*)(a.xbase + c.r0 * a.xstride + 4 * (int64_t)(g < a.F ? g : 0));
+  }
+  if (SUMS && tid < c.ne) {
+    double K;
+    int64_t Ki;
+    extra_shift(a.ex[tid], c.r0, K, Ki);
+    m.s_eK[tid] = K;
+    m.s_eKi[tid] = Ki;
+  }
+  if (self) {
+    for (int k = 0; k < 8; ++k) m.s_ex[c.wave * 8 + k] = 0.0;
+  }
+  lds_barrier();
+  {
+    double K[CPL], mx[CPL];
+    bool fin = true;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) {
+      K[i] = (double)m.s_K[c.cl0 + i];
+      mx[i] = 0.0;
+    }
+    const char* col0 = a.xbase + 4 * (int64_t)(colv ? c.gcol(c.cl0) : 0);
+    const int ns = nrow < NSAMP ? (int)nrow : NSAMP;
+    // SB rows per wave in flight: sample k is row r0 + k (nrow - 1) / (ns - 1)
+    for (int k0 = c.wave; k0 < ns; k0 += NW * SB) {
+      float x[SB][CPL];
+#pragma unroll
+      for (int u = 0; u < SB; ++u) {
+        const int k = min(k0 + NW * u, ns - 1);
+        // 32-bit: nrow <= 2^16 rows per block and k < NSAMP
+        const int64_t r = c.r0 + (ns > 1 ? (int)((unsigned)k * (unsigned)(nrow - 1) / (unsigned)(ns - 1)) : 0);
+        if constexpr (CPL == 4) {
+          const fl4 v = *(const fl4*)(col0 + r * a.xstride);
+#pragma unroll
+          for (int i = 0; i < 4; ++i) x[u][i] = v[i];
+        } else {
+          const fl2 v = *(const fl2*)(col0 + r * a.xstride);
+#pragma unroll
+          for (int i = 0; i < 2; ++i) x[u][i] = v[i];
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < SB; ++u)
+#pragma unroll
+        for (int i = 0; i < CPL; ++i) {
+          fin &= __builtin_isfinite(x[u][i]);
+          mx[i] = fmax(mx[i], fabs((double)x[u][i] - K[i]));
+        }
+    }
+    if (SUMS && !fin && colv) c.over = true;
+#pragma unroll
+    for (int i = 0; i < CPL; ++i) m.red[c.wave * NC + c.cl0 + i] = mx[i];
+  }
+  lds_barrier();
+  for (int k = tid; k < NC; k += kThreads) {
+    double mx = m.red[k];
+#pragma unroll
+    for (int w = 1; w < NW; ++w) mx = fmax(mx, m.red[w * NC + k]);
+    const float K = m.s_K[k];
+    const bool valid = c.gcol(k) < a.F && __builtin_isfinite(mx) && __builtin_isfinite(K);
+    const int s = grid_exp(mx, K);
+    m.s_exp[k] = s;
+    m.s_sc[k] = valid ? ldexpf(1.0f, s) : 0.0f;
+    m.s_nks[k] = valid ? -K * ldexpf(1.0f, s) : 0.0f;
+  }
+  lds_barrier();
+
+  // running sums of the diagonal pair: column sums, strips with the extras
+  double S[CPL], strip[NE][CPL];
+#pragma unroll
+  for (int i = 0; i < CPL; ++i) {
+    S[i] = 0.0;
+#pragma unroll
+    for (int e = 0; e < NE; ++e) strip[e][i] = 0.0;
+  }
+  Pending<CPL> pd;
+  auto commit = [&]() {
+    if constexpr (SUMS) {
+#pragma unroll
+      for (int i = 0; i < CPL; ++i) {
+        const double pw = ldexp(1.0, -m.s_exp[c.cl0 + i]);
+        S[i] = __builtin_fma((double)pd.is[i], pw, S[i]);
+#pragma unroll
+        for (int e = 0; e < NE; ++e)
+          if (e < c.ne) strip[e][i] = __builtin_fma(pd.sp[e][i], pw, strip[e][i]);
+      }
     }
     if (self) {
-      int t = 0;
+      double* x = m.s_ex + c.wave * 8;
+      int tq = 0;
 #pragma unroll
-      for (int e = 0; e < wide::kSyrkMaxExtra; ++e) {
-        if (e < ne) {
+      for (int e = 0; e < NE; ++e) {
+        if (e < c.ne) x[e] += pd.es[e];
 #pragma unroll
-          for (int j = 0; j < NR; ++j) eS[e] += de[e][j];
-        }
-#pragma unroll
-        for (int f = e; f < wide::kSyrkMaxExtra; ++f, ++t)
-          if (f < ne) {
-#pragma unroll
-            for (int j = 0; j < NR; ++j) eQ[t] = __builtin_fma(de[e][j], de[f][j], eQ[t]);
-          }
+        for (int f = e; f < NE; ++f, ++tq)
+          if (f < c.ne) x[NE + tq] += pd.eq[tq];
       }
     }
-    if (w0 + WR < r1) load_window(w0 + WR);  // in flight during the matrix-core phase
-    __syncthreads();                        // digits complete
-    // ---- matrix cores: one tile at a time, five FP32 levels ----
+  };
+  const WaveTiles wt = wave_tiles<DIAG>(c.wave, half);
+  // tiles that hold vector columns: a prefix of the wave's list
+  int nt = 0;
 #pragma unroll
-    for (int u = 0; u < MAXT; ++u) {
-      if (u >= nt) break;
-      int ti, tj;
-      wave_tile<DIAG>(u, wave, ti, tj);
-      if (A * G + 32 * ti >= a.F || B * G + 32 * tj >= a.F) continue;
-      f16v L[5];
+  for (int u = 0; u < MT; ++u)
+    if (u < wt.n && A * G + 32 * wt.ti[u] < a.F && B * G + 32 * wt.tj[u] < a.F) nt = u + 1;
+  // (a diagonal pair's lists put the tiles a short last group leaves out last,
+  // except wave 3's transposed (3, 0), which is valid whenever (3, 3) is)
+  nt = __builtin_amdgcn_readfirstlane(nt);
+  i16 L[MT][5];
 #pragma unroll
-      for (int l = 0; l < 5; ++l) L[l] = (f16v){};
-      const int sa = 32 * ti + q, sb = boff + 32 * tj + q;
+  for (int u = 0; u < MT; ++u)
 #pragma unroll
-      for (int k16 = 0; k16 < WR / 16; ++k16) {
-        const int kr = 16 * k16 + 8 * h;
-        bf8 fa[3], fb[3];
-#pragma unroll
-        for (int d = 0; d < 3; ++d) {
-          fa[d] = __builtin_bit_cast(bf8, *(const u4*)&sm.dig[d][lpos(sa)][kr]);
-          fb[d] = __builtin_bit_cast(bf8, *(const u4*)&sm.dig[d][lpos(sb)][kr]);
-        }
-        // level order interleaved so that dependent products are apart
-        L[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], fb[0], L[0], 0, 0, 0);
-        L[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], fb[1], L[1], 0, 0, 0);
-        L[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[0], fb[2], L[2], 0, 0, 0);
-        L[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], fb[2], L[3], 0, 0, 0);
-        L[4] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[2], fb[2], L[4], 0, 0, 0);
-        L[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], fb[0], L[1], 0, 0, 0);
-        L[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[1], fb[1], L[2], 0, 0, 0);
-        L[3] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[2], fb[1], L[3], 0, 0, 0);
-        L[2] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(fa[2], fb[0], L[2], 0, 0, 0);
-      }
-      // window flush: exact FP32 level sums, scaled into FP64
-      const double pj = sm.pw[sb];
-#pragma unroll
-      for (int k = 0; k < 16; ++k) {
-        const int i = (k >> 2) * 8 + h * 4 + (k & 3);
-        const double pij = sm.pw[32 * ti + i] * pj;
-        double t = (double)L[4][k];
-        t = __builtin_fma(t, 0x1p-9, (double)L[3][k]);
-        t = __builtin_fma(t, 0x1p-9, (double)L[2][k]);
-        t = __builtin_fma(t, 0x1p-9, (double)L[1][k]);
-        t = __builtin_fma(t, 0x1p-9, (double)L[0][k]);
-        Q[u][k] = __builtin_fma(t, pij, Q[u][k]);
+    for (int l = 0; l < 5; ++l) L[u][l] = (i16){};
+
+  typename Ctx<DIAG, SUMS>::Raw raw;
+  if (nsub > 2) c.template wait_dma<2>();
+  else if (nsub > 1) c.template wait_dma<1>();
+  else c.template wait_dma<0>();
+  c.fetch(0, raw);
+  if (SR > nrow) c.template digitize<true>(0, 0, raw, pd);
+  else c.template digitize<false>(0, 0, raw, pd);
+  lds_barrier();
+  commit();
+  // Sub-step t: DMA of t + 3 into the stage of t (fetched into registers
+  // one sub-step ago), fetch of t + 1 (its DMA was issued two sub-steps
+  // ago), products of t, digits of t + 1 (the vector work can fill the
+  // matrix-core shadow).  Branch-free in the main loop; the last three
+  // sub-steps are peeled.
+  // row pointers of sub-step t + 3 for the DMA inside the block
+  const int64_t step_bytes = (int64_t)SR * a.xstride;
+  const char* rp;
+  const char* ep = nullptr;
+  int64_t ep_step = 0;
+  {
+    const int dc = DIAG ? A * G + 4 * (c.lane & 31) : c.gcol(4 * c.lane);
+    const int64_t col = dc < a.F ? dc : 0;
+    const int64_t r = c.r0 + 3 * SR + RW * c.wave + (DIAG ? c.h : 0);
+    rp = a.xbase + r * a.xstride + 4 * col;
+    if (SUMS && c.ne > 0) {
+      const int e = c.lane >> 3, wd = (c.lane >> 2) & 1, j = c.lane & 3;
+      if (c.lane < 16 && e < c.ne) {
+        ep = a.ex[e].base + (c.r0 + 3 * SR + RW * c.wave + j) * a.ex[e].stride + 4 * wd;
+        ep_step = (int64_t)SR * a.ex[e].stride;
       }
     }
   }
-  // ---- record ----
+  auto step = [&](int64_t t, int s_t, auto more_c, auto issue_c, auto later_c, auto tail_c) __attribute__((always_inline)) {
+    constexpr bool MORE = decltype(more_c)::value;
+    constexpr int ISSUE = decltype(issue_c)::value;  // 0: none, 1: inside the block, 2: clamped
+    constexpr int LATER = decltype(later_c)::value;
+    constexpr bool TAIL = decltype(tail_c)::value;
+    const int s_next = s_t == NST - 1 ? 0 : s_t + 1;  // stage of t + 1
+    if constexpr (ISSUE == 1) c.issue_inside(s_t, rp, ep);  // t + 3 lands in the stage of t
+    if constexpr (ISSUE == 2) c.issue(t + 3);
+    if constexpr (MORE) {
+      c.template wait_dma<LATER>();
+      c.fetch(s_next, raw);
+    }
+    mma_step<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, L);
+    if constexpr (MORE) c.template digitize<TAIL>(t + 1, s_next, raw, pd);
+    lds_barrier();
+    if constexpr (MORE) commit();
+  };
+  using T_ = std::true_type;
+  using F_ = std::false_type;
+  using I0 = std::integral_constant<int, 0>;
+  using I1 = std::integral_constant<int, 1>;
+  using I2 = std::integral_constant<int, 2>;
+  int64_t t = 0;
+  int s_t = 0;  // t % NST
+  // sub-steps t + 3 that lie wholly inside the block
+  for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; ++t) {
+    step(t, s_t, T_{}, I1{}, I2{}, F_{});
+    rp += step_bytes;
+    ep += ep_step;
+    s_t = s_t == NST - 1 ? 0 : s_t + 1;
+  }
+  for (; t + 3 < nsub; ++t) {
+    step(t, s_t, T_{}, I2{}, I2{}, F_{});
+    s_t = s_t == NST - 1 ? 0 : s_t + 1;
+  }
+  if (t + 2 < nsub) {
+    step(t, s_t, T_{}, I0{}, I1{}, F_{});
+    ++t;
+    s_t = s_t == NST - 1 ? 0 : s_t + 1;
+  }
+  if (t + 1 < nsub) {
+    if (c.r0 + (t + 2) * SR > c.r1) step(t, s_t, T_{}, I0{}, I0{}, T_{});
+    else step(t, s_t, T_{}, I0{}, I0{}, F_{});
+    ++t;
+    s_t = s_t == NST - 1 ? 0 : s_t + 1;
+  }
+  step(t, s_t, F_{}, I0{}, I0{}, F_{});
+  if (c.over) a.ovf[b] = 1;  // this block is computed again in FP64
+  if (c.bad) atomicOr(&a.status->bits, ST_INEXACT);
+
+  // ---- tiles: levels combined, scaled by the grids, into the record ----
   const int p = a.p;
-  uint64_t* out = a.rec + b * rec_words(p);
 #pragma unroll
-  for (int u = 0; u < MAXT; ++u) {
+  for (int u = 0; u < MT; ++u) {
     if (u >= nt) break;
-    int ti, tj;
-    wave_tile<DIAG>(u, wave, ti, tj);
+    const int sbl = (DIAG ? 0 : G) + 32 * wt.tj[u] + c.q;
+    const int cb = B * G + 32 * wt.tj[u] + c.q;
+    const int ub = a.col_of[cb < a.F ? cb : 0];
+    const int sb = m.s_exp[sbl];
 #pragma unroll
     for (int k = 0; k < 16; ++k) {
-      const int i = (k >> 2) * 8 + h * 4 + (k & 3);
-      const int ca = A * G + 32 * ti + i, cb = B * G + 32 * tj + q;
-      if (ca < a.F && cb < a.F && ca <= cb) {
-        const int ua = a.col_of[ca], ub = a.col_of[cb];
-        out[2 + 2 * p + tri(p, min(ua, ub), max(ua, ub))] = (uint64_t)__double_as_longlong(Q[u][k]);
+      const int sal = 32 * wt.ti[u] + (k >> 2) * 8 + c.h * 4 + (k & 3);
+      const int ca = A * G + sal;
+      if (ca < a.F && cb < a.F && (ca <= cb || wt.ti[u] != wt.tj[u])) {
+        double P = (double)L[u][4][k];
+        P = __builtin_fma(P, 0x1p-8, (double)L[u][3][k]);
+        P = __builtin_fma(P, 0x1p-8, (double)L[u][2][k]);
+        P = __builtin_fma(P, 0x1p-8, (double)L[u][1][k]);
+        P = __builtin_fma(P, 0x1p-8, (double)L[u][0][k]);
+        const int ua = a.col_of[ca];
+        out[2 + 2 * p + tri(p, min(ua, ub), max(ua, ub))] =
+            (uint64_t)__double_as_longlong(ldexp(P, 32 - m.s_exp[sal] - sb));
       }
     }
   }
-  if (bad) atomicOr(&a.status->bits, ST_INEXACT);
-  if (!DIAG) return;
-  // column sums and extra strips: fixed-order sums over the 8 row groups
-  auto reduce_write = [&](const double (&v)[4], int extra) {
-    __syncthreads();
+  if (!SUMS) return;
+
+  // ---- column sums, K, strips: fixed-order sums over the waves ----
+  auto reduce_write = [&](const double (&v)[CPL], int extra) {
+    lds_barrier();
 #pragma unroll
-    for (int i = 0; i < 4; ++i) sm.red[rg][sl0 + i] = v[i];
-    __syncthreads();
-    if (threadIdx.x < G) {
-      const int s = threadIdx.x, c = A * G + s;
-      double t = sm.red[0][s];
+    for (int i = 0; i < CPL; ++i) m.red[c.wave * NC + c.cl0 + i] = v[i];
+    lds_barrier();
+    for (int k = tid; k < NC; k += kThreads) {
+      const int cg = A * G + k;
+      double sum = m.red[k];
 #pragma unroll
-      for (int g = 1; g < 8; ++g) t += sm.red[g][s];
-      if (c < a.F) {
-        const int uc = a.col_of[c];
+      for (int w = 1; w < NW; ++w) sum += m.red[w * NC + k];
+      if (cg < a.F) {
+        const int uc = a.col_of[cg];
         if (extra < 0) {
-          out[2 + p + uc] = (uint64_t)__double_as_longlong(t);
-          out[2 + uc] = (uint64_t)__double_as_longlong(sm.K[s]);
+          out[2 + p + uc] = (uint64_t)__double_as_longlong(sum);
+          out[2 + uc] = (uint64_t)__double_as_longlong((double)m.s_K[k]);
         } else {
           const int ue = a.col_of[a.F + extra];
-          out[2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))] = (uint64_t)__double_as_longlong(t);
+          out[2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))] = (uint64_t)__double_as_longlong(sum);
         }
       }
     }
   };
   reduce_write(S, -1);
-  for (int e = 0; e < ne; ++e) reduce_write(strip[e], e);
+#pragma unroll
+  for (int e = 0; e < NE; ++e)
+    if (e < c.ne) reduce_write(strip[e], e);
   if (A == 0) {
-    // extras' sums and products: row-group partials held by lanes q == 0
-    __syncthreads();
-    if (q == 0) {
-      int t = 0;
-#pragma unroll
-      for (int e = 0; e < wide::kSyrkMaxExtra; ++e) {
-        sm.red[rg][e] = eS[e];
-#pragma unroll
-        for (int f = e; f < wide::kSyrkMaxExtra; ++f, ++t) sm.red[rg][wide::kSyrkMaxExtra + t] = eQ[t];
-      }
-    }
-    __syncthreads();
-    if (threadIdx.x == 0) {
-      int t = 0;
-      for (int e = 0; e < ne; ++e) {
-        double s = sm.red[0][e];
-        for (int g = 1; g < 8; ++g) s += sm.red[g][e];
+    lds_barrier();
+    if (tid == 0) {
+      int tq = 0;
+      for (int e = 0; e < c.ne; ++e) {
+        double s = m.s_ex[e];
+        for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + e];
         const int ue = a.col_of[a.F + e];
         out[2 + p + ue] = (uint64_t)__double_as_longlong(s);
-        out[2 + ue] = shift_word(a.ex[e].isint, a.ex[e].kind, eK[e], eKi[e]);
+        out[2 + ue] = shift_word(a.ex[e].isint, a.ex[e].kind, m.s_eK[e], m.s_eKi[e]);
       }
-      for (int e = 0; e < wide::kSyrkMaxExtra; ++e)
-        for (int f = e; f < wide::kSyrkMaxExtra; ++f, ++t)
-          if (f < ne) {
-            double s = sm.red[0][wide::kSyrkMaxExtra + t];
-            for (int g = 1; g < 8; ++g) s += sm.red[g][wide::kSyrkMaxExtra + t];
+      for (int e = 0; e < NE; ++e)
+        for (int f = e; f < NE; ++f, ++tq)
+          if (f < c.ne) {
+            double s = m.s_ex[NE + tq];
+            for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + NE + tq];
             const int ue = a.col_of[a.F + e], uf = a.col_of[a.F + f];
             out[2 + 2 * p + tri(p, min(ue, uf), max(ue, uf))] = (uint64_t)__double_as_longlong(s);
           }
-      out[0] = (uint64_t)(r1 - r0);
+      out[0] = (uint64_t)nrow;
       out[1] = 0;
     }
   }
 }
 
-__global__ __launch_bounds__(kThreads, 1) void k_syrk_split(wide::SyrkArgs a) {
-  __shared__ __attribute__((aligned(16))) Smem sm;
+__global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
+  __shared__ __attribute__((aligned(16))) unsigned char s_ring[NST * STB];
+  __shared__ __attribute__((aligned(16))) union {
+    int dig[2 * 3 * 8 * PITCH_MAX];
+    double red[NW * 2 * G];
+  } s_u;
+  __shared__ int s_exp[2 * G];
+  __shared__ float s_K[2 * G], s_sc[2 * G], s_nks[2 * G];
+  __shared__ double s_eK[NE];
+  __shared__ int64_t s_eKi[NE];
+  __shared__ double s_ex[NW * 8];
   const int64_t id = blockIdx.x;
   const int64_t xcd = id & 7, y = id >> 3;
   const int t = (int)(y % a.npairs);
   const int64_t b = (y / a.npairs) * 8 + xcd;
   if (b >= a.nblocks) return;
-  const int A = a.pairs[t].x, B = a.pairs[t].y;
-  if (A == B) pair_block<true>(a, sm, b, A, B);
-  else pair_block<false>(a, sm, b, A, B);
+  const int A = a.pairs[t].x & 15, B = a.pairs[t].y, half = a.pairs[t].x >> 4;
+  Lds m;
+  m.ring = s_ring;
+  m.dig = s_u.dig;
+  m.red = s_u.red;
+  m.s_exp = s_exp;
+  m.s_K = s_K;
+  m.s_sc = s_sc;
+  m.s_nks = s_nks;
+  m.s_eK = s_eK;
+  m.s_eKi = s_eKi;
+  m.s_ex = s_ex;
+  if (A != B) pair_block<false, false>(a, m, b, A, B, half);
+  else if (half == 0) pair_block<true, true>(a, m, b, A, B, 0);
+  else pair_block<true, false>(a, m, b, A, B, 1);
+}
+
+__global__ void k_zero_flags(int* f, int64_t n) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f[i] = 0;
 }
 
 }  // namespace syrk
 
 void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s) {
+  hipLaunchKernelGGL(syrk::k_zero_flags, dim3((unsigned)((a.nblocks + 255) / 256)), dim3(256), 0, s, a.ovf,
+                     a.nblocks);
   const int64_t nb8 = (a.nblocks + 7) / 8 * 8;
-  hipLaunchKernelGGL(syrk::k_syrk_split, dim3((unsigned)(nb8 * a.npairs)), dim3(syrk::kThreads), 0, s, a);
+  hipLaunchKernelGGL(syrk::k_syrk_i8, dim3((unsigned)(nb8 * a.npairs)), dim3(syrk::kThreads), 0, s, a);
 }
 
 }  // namespace st

@@ -195,3 +195,34 @@ def test_file_errors(tmp_path):
         assert e.value.code == L.STATS_E_ARG
     finally:
         L.stats_close(h)
+
+
+def test_decimal_range_boundary():
+    """The exact-ratio conversion takes decimal fields w * 10^q (w the
+    written significand, q the exponent of its last digit) below 10^73 in
+    magnitude with q >= -57: the values just inside parse to the correctly
+    rounded double; just outside (1e74, a last digit at 10^-58) the field is
+    refused with STATS_E_PARSE and the line's offset, never rounded wrongly."""
+    import struct
+    L = lib()
+    cols = [(L.STATS_F64, 0, 0, 0), (L.STATS_F64, 0, 8, 0)]
+    inside = [b"1e73", b"-9.999999999999999e72", b"1e-57", b"-1.5e-56", b"123456789012345678901e52",
+              b"0.000000000000000000000000000000000000000000000000000000001"]
+    outside = [b"1e74", b"9e73", b"1e-58", b"1.0e-57", b"1e100", b"-1e-300"]
+    h = L.stats_open(L.make_config(cols, [16], stream=current_stream()))
+    try:
+        txt = b"".join(v + b",1\n" for v in inside)
+        out = _empty(16 * len(inside))
+        rows, used = L.stats_text_to_binary(h, _dev_bytes(txt), len(txt), [out], len(inside), is_last=True)
+        assert rows == len(inside) and used == len(txt)
+        got = out[:16 * len(inside)].cpu().numpy().view(np.float64).reshape(-1, 2)[:, 0]
+        for g, v in zip(got, inside):
+            ref = float(v.decode())
+            assert struct.pack("<d", g) == struct.pack("<d", ref), (v, g, ref)
+        for v in outside:
+            line = b"2,3\n" + v + b",1\n"
+            with pytest.raises(L.StatsError) as e:
+                L.stats_text_to_binary(h, _dev_bytes(line), len(line), [_empty(32)], 2, is_last=True)
+            assert e.value.code == L.STATS_E_PARSE and "offset 4" in str(e.value), v
+    finally:
+        L.stats_close(h)

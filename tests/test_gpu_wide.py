@@ -1,6 +1,7 @@
 """GPU parity of the wide-table path (p > 16, matrix cores) against the CPU
-oracle: FP64 mode (exact for integer columns) and split-BF16 mode (exact for
-integer columns, floating columns within 1e-9 correlation-scaled)."""
+oracle: FP64 mode (exact for integer columns) and split mode (int8 digits for
+FP32 row-major tables, BF16 digits for other layouts; integer columns exact,
+floating columns within 1e-9 correlation-scaled)."""
 import numpy as np
 import pytest
 
@@ -41,7 +42,7 @@ def test_p32_table1_extended(n, prec):
     print(f"p32 n={n} {prec}", flush=True)
     L = lib()
     x = datagen.groups_aos(4, n, row0=0, a0=1)
-    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT_BF16
+    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT
     raw, fin = _run(L, _c4_config(L, precision=precision), [to_dev(x)], n, 32)
     st = oracle.sufficient_stats(oracle.columns_of(x), C4_INT)
     if prec == "fp64":
@@ -81,7 +82,7 @@ def test_gaussian_fp32_with_identifier(p, prec):
     L = lib()
     x = gauss.rows_host(3, n, p - 1)
     ident = np.arange(1, n + 1, dtype=np.int32)
-    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT_BF16
+    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT
     raw, fin = _run(L, _c3_config(L, p, precision=precision, block_rows=4096),
                     [to_dev(x), to_dev(ident)], n, p)
     is_int = [True] + [False] * (p - 1)
@@ -105,17 +106,53 @@ def test_gaussian_fp32_with_identifier(p, prec):
         assert abs(raw["C_f64"][0, j] - ref_c) <= 1e-9 * abs(ref_c)
 
 
-def test_split_and_fp64_agree_and_split_is_exact_on_fp32_grid():
+def test_split_and_fp64_agree_on_gaussian_fp32():
     L = lib()
     p, n = 65, 30_000
     x = gauss.rows_host(5, n, p - 1)
     ident = np.arange(1, n + 1, dtype=np.int32)
     planes = [to_dev(x), to_dev(ident)]
     _, f64 = _run(L, _c3_config(L, p, precision=L.STATS_PREC_FP64), planes, n, p)
-    _, spl = _run(L, _c3_config(L, p, precision=L.STATS_PREC_SPLIT_BF16), planes, n, p)
-    # C3-like FP32 data is shifted within its binade: the digits are exact, so
-    # the two modes differ only by FP64 summation order
+    _, spl = _run(L, _c3_config(L, p, precision=L.STATS_PREC_SPLIT), planes, n, p)
+    # C3-like FP32 data (large means, spread a few binades below them) lies
+    # on each block's grid: the digits are exact, so the two modes differ
+    # only by FP64 summation order
     assert corr_scaled_err(spl["cov"], f64["cov"]) <= 1e-13
+
+
+@pytest.mark.parametrize("case", ["spike", "nan", "inf"])
+def test_split_blocks_off_grid_fall_back_to_fp64(case):
+    """A value 4096 times its column's spread that is not one of the rows
+    sampled for the block's grids, a NaN or an infinity: the block is
+    computed again on the FP64 matrix cores, so the split mode still matches
+    the FP64 mode to summation-order noise (NaN and infinity where the FP64
+    mode has them)."""
+    print(f"off-grid {case}", flush=True)
+    L = lib()
+    p, n = 65, 50_000
+    x = gauss.rows_host(11, n, p - 1)
+    r, c = 20_001, 3  # row 20001 is not one of the 1024 rows sampled from its 8192-row block
+    x[r, c] = {"spike": x[r, c] * 4096.0, "nan": np.nan, "inf": np.inf}[case]
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    planes = [to_dev(x), to_dev(ident)]
+    outs = []
+    for prec in (L.STATS_PREC_FP64, L.STATS_PREC_SPLIT):
+        h = L.stats_open(_c3_config(L, p, precision=prec, block_rows=8192))
+        try:
+            L.stats_accumulate(h, planes, n)
+            outs.append(L.stats_raw(h, p))
+        finally:
+            L.stats_close(h)
+    f64, spl = outs
+    a, b = f64["C_f64"], spl["C_f64"]
+    assert np.array_equal(np.isnan(a), np.isnan(b)) and np.array_equal(np.isinf(a), np.isinf(b))
+    ok = np.isfinite(a)
+    d = np.sqrt(np.abs(np.diag(np.where(ok, a, 1.0))))
+    assert np.max(np.abs(a[ok] - b[ok]) / np.outer(d, d)[ok]) <= 1e-13
+    if case == "spike":
+        st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(p - 1)], [True] + [False] * (p - 1))
+        ref = float(st.C_exact[oracle.tri_index(p, c + 1, c + 1)])
+        assert abs(b[c + 1, c + 1] - ref) <= 1e-12 * abs(ref)
 
 
 @pytest.mark.parametrize("n", [1, 63, 64, 65, 40_001])
@@ -135,7 +172,7 @@ def test_split_two_extras_partial_group(n):
            [(L.STATS_F32, 0, 4 * j, 0) for j in range(F)] + [(L.STATS_F64, 2, 0, 0)]
     p = F + 2
     cfg = L.make_config(cols, [4 * (F + 4), 8, 8], stream=current_stream(),
-                        precision=L.STATS_PREC_SPLIT_BF16, block_rows=8192)
+                        precision=L.STATS_PREC_SPLIT, block_rows=8192)
     raw, fin = _run(L, cfg, [to_dev(x), to_dev(ident), to_dev(extra)], n, p)
     is_int = [True] + [False] * (F + 1)
     st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(F)] + [extra], is_int)
@@ -193,3 +230,45 @@ def test_fp64_rows_of_256_bytes_inexact_integer():
         assert e.value.code == L.STATS_E_INEXACT
     finally:
         L.stats_close(h)
+
+
+def test_auto_precision_picks_int8_kernel_or_fp64():
+    """STATS_PREC_AUTO: FP32 columns in one row-major plane take the int8
+    kernel (same result as STATS_PREC_SPLIT, bit for bit); the same values
+    with every column on a plane of its own take the FP64 path (same result
+    as STATS_PREC_FP64, bit for bit), since the general split kernel would
+    let an outlier coarsen its block's grid."""
+    L = lib()
+    p, n = 25, 40_000  # 25 planes in the second layout (at most 32)
+    x = gauss.rows_host(13, n, p - 1)
+    x[12_345, 7] *= 4096.0
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    rm = [to_dev(x), to_dev(ident)]
+    res = {}
+    for name, prec in (("auto", L.STATS_PREC_AUTO), ("split", L.STATS_PREC_SPLIT)):
+        h = L.stats_open(_c3_config(L, p, precision=prec, block_rows=8192))
+        try:
+            L.stats_accumulate(h, rm, n)
+            res[name] = L.stats_raw(h, p)
+        finally:
+            L.stats_close(h)
+    assert np.array_equal(res["auto"]["C_f64"], res["split"]["C_f64"])
+    # one plane per column
+    colplanes = [to_dev(np.ascontiguousarray(x[:, j])) for j in range(p - 1)] + [to_dev(ident)]
+    cols = [(L.STATS_I32, p - 1, 0, L.STATS_COL_IDENTIFIER)] + \
+           [(L.STATS_F32, j, 0, 0) for j in range(p - 1)]
+    for name, prec in (("auto", L.STATS_PREC_AUTO), ("fp64", L.STATS_PREC_FP64)):
+        h = L.stats_open(L.make_config(cols, [4] * p, stream=current_stream(), precision=prec,
+                                       block_rows=8192))
+        try:
+            L.stats_accumulate(h, colplanes, n)
+            res["soa_" + name] = L.stats_raw(h, p)
+        finally:
+            L.stats_close(h)
+    assert np.array_equal(res["soa_auto"]["C_f64"], res["soa_fp64"]["C_f64"])
+    # the outlier's column against the oracle in both layouts
+    cols_o = [ident] + [x[:, j] for j in range(p - 1)]
+    st = oracle.sufficient_stats(cols_o, [True] + [False] * (p - 1))
+    ref = float(st.C_exact[oracle.tri_index(p, 8, 8)])
+    for k in ("auto", "soa_auto"):
+        assert abs(res[k]["C_f64"][8, 8] - ref) <= 1e-12 * ref, k
