@@ -200,7 +200,9 @@ int stats_accumulate_file(stats_ctx* h, const char* path, int64_t offset, int64_
  * are consumed unless is_last != 0, when a final unterminated line counts
  * too; *bytes_consumed receives the bytes used (the caller passes the rest
  * again at the front of the next chunk).  A malformed field gives
- * STATS_E_PARSE with its byte offset in stats_last_error(). */
+ * STATS_E_PARSE with the byte offset of its line in stats_last_error(),
+ * counted from the start of the handle's text: the bytes that earlier
+ * calls since stats_open / stats_reset consumed included. */
 int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
                           int32_t is_last, int64_t* bytes_consumed);
 
@@ -219,8 +221,9 @@ int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbytes, int32_t
  * FP32 output would round twice).  *rows_out = lines converted; the chunk
  * may hold at most max_rows lines (else STATS_E_ARG, nothing written).
  * STATS_E_PARSE: a malformed field, an integer outside int32 for an I32
- * column or beyond 2^53 for an F64 one; the byte offset of its line is in
- * stats_last_error() and the output rows are then unspecified.  Returns
+ * column or beyond 2^53 for an F64 one; the byte offset of its line (from
+ * the start of the handle's text, as above) is in stats_last_error() and
+ * the output rows are then unspecified.  Returns
  * after the conversion has finished.  p <= 16. */
 int stats_text_to_binary(stats_ctx* h, const char* buf, int64_t nbytes, int32_t mem_kind,
                          int32_t is_last, void* const* out_planes, int64_t max_rows,

@@ -29,11 +29,15 @@
 // few binades of the shift (and integers below 2^21) lie on it, so their
 // products are exact.
 //
-// A block with a value beyond its column's limit, or a non-finite value, is
+// A block with a value beyond its column's limit, a value off its grid
+// (x 2^s not an integer: one v_fract per value), or a non-finite value is
 // flagged (ovf[b]) by the diagonal pair that owns the column (every column
 // belongs to one); the FP64 matrix-core routine of wide.hip then computes
 // that block's whole record again (launch_wide_fixup), so every block is
-// either exact on its grid or FP64.
+// either exact on its grid or FP64.  Each workgroup also finds the lowest set
+// bit of its first 128 sampled rows: when one lies below the grid spacing
+// the block cannot be exact (zero-mean data with full significands, say), and
+// the workgroup flags it and stops before the main loop.
 //
 // Work split: vector columns form groups of 128.  A workgroup owns one block
 // of rows and one half of a pair of groups (A, B), A <= B: two tile rows of
@@ -391,13 +395,13 @@ struct Ctx {
   // finiteness.
   template <bool TAIL>
   __device__ __attribute__((always_inline)) void digitize(int64_t t, int stage_i, Raw& r, Pending<CPL>& pd) {
-    float sc[CPL], nks[CPL], mx[CPL], fs[CPL];
+    float sc[CPL], nks[CPL], mx[CPL], fs[CPL], fo[CPL];
     int sw[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       sc[i] = s_sc[cl0 + i];
       nks[i] = s_nks[cl0 + i];
-      mx[i] = fs[i] = 0.0f;
+      mx[i] = fs[i] = fo[i] = 0.0f;
       sw[i] = 0;
 #pragma unroll
       for (int e = 0; e < NE; ++e) pd.sp[e][i] = 0.0;
@@ -440,6 +444,11 @@ struct Ctx {
           const float fr = y + kRound;
           w[jj] = __float_as_int(fr) + kBias;  // v + 0x8080: bytes d2 + 128, d1 + 128, d0
           if constexpr (SUMS) {
+            // on the grid: x 2^s is an integer (K is too: it is the first
+            // row); the fraction is exact, so this test is too
+            float xf = __builtin_amdgcn_fractf(r.x[4 * g + jj][i] * sc[i]);
+            if (TAIL) xf = (rb + 4 * g + jj < r1) ? xf : 0.0f;
+            fo[i] = fmaxf(fo[i], xf);
             mx[i] = fmaxf(mx[i], fabsf(y));
             fs[i] += y;  // NaN and infinity show here
             sw[i] += w[jj];
@@ -470,7 +479,7 @@ struct Ctx {
     if constexpr (SUMS) {
 #pragma unroll
       for (int i = 0; i < CPL; ++i) {
-        over |= !(mx[i] <= kVlim) | !(fabsf(fs[i]) <= 3.0e38f);
+        over |= !(mx[i] <= kVlim) | !(fabsf(fs[i]) <= 3.0e38f) | !(fo[i] == 0.0f);
         pd.is[i] = sw[i] - RW * 0x8080;
       }
     }
@@ -526,6 +535,7 @@ struct Lds {
   double* s_eK;
   int64_t* s_eKi;
   double* s_ex;     // [NW][8]: extras' per-wave sums and products
+  int* s_flag;      // sampled values off their grid: the block goes to FP64
 };
 
 // One block of rows and one pair of column groups (A, B).
@@ -567,7 +577,9 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   for (int k = tid; k < NC; k += kThreads) {
     const int g = c.gcol(k);
     m.s_K[k] = *(const float*)(a.xbase + c.r0 * a.xstride + 4 * (int64_t)(g < a.F ? g : 0));
+    m.s_exp[k] = 0x7FFFFFFF;  // lowest set bit of the sampled values, below
   }
+  if (tid == 0) m.s_flag[0] = 0;
   if (SUMS && tid < c.ne) {
     double K;
     int64_t Ki;
@@ -581,11 +593,13 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   lds_barrier();
   {
     double K[CPL], mx[CPL];
+    int lb[CPL];
     bool fin = true;
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       K[i] = (double)m.s_K[c.cl0 + i];
       mx[i] = 0.0;
+      lb[i] = 0x7FFFFFFF;
     }
     const char* col0 = a.xbase + 4 * (int64_t)(colv ? c.gcol(c.cl0) : 0);
     const int ns = nrow < NSAMP ? (int)nrow : NSAMP;
@@ -614,10 +628,27 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
           fin &= __builtin_isfinite(x[u][i]);
           mx[i] = fmax(mx[i], fabs((double)x[u][i] - K[i]));
         }
+      if (k0 == c.wave) {
+        // the first NW x SB samples: exponent of each value's lowest set
+        // bit (x = sig 2^(E - 150) for a normal FP32 value)
+#pragma unroll
+        for (int u = 0; u < SB; ++u)
+#pragma unroll
+          for (int i = 0; i < CPL; ++i) {
+            const uint32_t bits = __float_as_uint(x[u][i]) & 0x7FFFFFFFu;
+            const uint32_t E = bits >> 23;
+            const uint32_t sig = E ? (bits & 0x7FFFFFu) | 0x800000u : bits;
+            const int l = (E ? (int)E : 1) - 150 + __builtin_ctz(sig | 0x80000000u);
+            lb[i] = sig ? min(lb[i], l) : lb[i];
+          }
+      }
     }
     if (SUMS && !fin && colv) c.over = true;
 #pragma unroll
-    for (int i = 0; i < CPL; ++i) m.red[c.wave * NC + c.cl0 + i] = mx[i];
+    for (int i = 0; i < CPL; ++i) {
+      m.red[c.wave * NC + c.cl0 + i] = mx[i];
+      atomicMin(&m.s_exp[c.cl0 + i], lb[i]);
+    }
   }
   lds_barrier();
   for (int k = tid; k < NC; k += kThreads) {
@@ -627,11 +658,20 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     const float K = m.s_K[k];
     const bool valid = c.gcol(k) < a.F && __builtin_isfinite(mx) && __builtin_isfinite(K);
     const int s = grid_exp(mx, K);
+    // a sampled value below the grid's spacing 2^-s: this block's values do
+    // not sit on a common grid (e.g. zero-mean data with full significands)
+    if (valid && m.s_exp[k] < -s) m.s_flag[0] = 1;
     m.s_exp[k] = s;
     m.s_sc[k] = valid ? ldexpf(1.0f, s) : 0.0f;
     m.s_nks[k] = valid ? -K * ldexpf(1.0f, s) : 0.0f;
   }
   lds_barrier();
+  if (m.s_flag[0]) {
+    // the whole block is recomputed in FP64; drain the row DMA first
+    c.template wait_dma<0>();
+    if (tid == 0) a.ovf[b] = 1;
+    return;
+  }
 
   // running sums of the diagonal pair: column sums, strips with the extras
   double S[CPL], strip[NE][CPL];
@@ -852,6 +892,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   __shared__ double s_eK[NE];
   __shared__ int64_t s_eKi[NE];
   __shared__ double s_ex[NW * 8];
+  __shared__ int s_flag;
   const int64_t id = blockIdx.x;
   const int64_t xcd = id & 7, y = id >> 3;
   const int t = (int)(y % a.npairs);
@@ -869,6 +910,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   m.s_eK = s_eK;
   m.s_eKi = s_eKi;
   m.s_ex = s_ex;
+  m.s_flag = &s_flag;
   if (A != B) pair_block<false, false>(a, m, b, A, B, half);
   else if (half == 0) pair_block<true, true>(a, m, b, A, B, 0);
   else pair_block<true, false>(a, m, b, A, B, 1);

@@ -219,10 +219,15 @@ def test_decimal_range_boundary():
         for g, v in zip(got, inside):
             ref = float(v.decode())
             assert struct.pack("<d", g) == struct.pack("<d", ref), (v, g, ref)
-        for v in outside:
+    finally:
+        L.stats_close(h)
+    for v in outside:
+        # a fresh handle each: offsets count from the start of a handle's text
+        h = L.stats_open(L.make_config(cols, [16], stream=current_stream()))
+        try:
             line = b"2,3\n" + v + b",1\n"
             with pytest.raises(L.StatsError) as e:
                 L.stats_text_to_binary(h, _dev_bytes(line), len(line), [_empty(32)], 2, is_last=True)
             assert e.value.code == L.STATS_E_PARSE and "offset 4" in str(e.value), v
-    finally:
-        L.stats_close(h)
+        finally:
+            L.stats_close(h)

@@ -191,6 +191,38 @@ def test_split_two_extras_partial_group(n):
         assert corr_scaled_err(fin["cov"], ref["cov"]) <= 1e-9
 
 
+@pytest.mark.parametrize("case", ["zero_mean", "one_value"])
+def test_split_values_off_their_grid_go_to_fp64(case):
+    """Values that do not sit on their block's fixed-point grid.  zero_mean:
+    N(0, 1) FP32 columns with full significands; the sampled rows already
+    show it, every block is recomputed in FP64.  one_value: integer-valued
+    FP32 columns (on the grid) with one 0.37 in a row that is not sampled;
+    only the per-value test sees it (rounded to the grid it would move its
+    column's cross products by ~3e-11 of their scale).  Split must match
+    FP64 mode to summation-order noise and the oracle to 1e-12."""
+    print(f"off-grid values {case}", flush=True)
+    L = lib()
+    p, n = 65, 50_000
+    rng = np.random.default_rng(17)
+    if case == "zero_mean":
+        x = rng.standard_normal((n, p - 1)).astype(np.float32)
+    else:
+        x = rng.integers(-10, 11, size=(n, p - 1)).astype(np.float32)
+        x[20_001, 3] = np.float32(0.37)  # row 20001: not sampled in its 8192-row block
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    planes = [to_dev(x), to_dev(ident)]
+    res = {}
+    for name, prec in (("fp64", L.STATS_PREC_FP64), ("split", L.STATS_PREC_SPLIT)):
+        res[name] = _run(L, _c3_config(L, p, precision=prec, block_rows=8192), planes, n, p)
+    scale = np.sqrt(np.abs(np.outer(np.diag(res["fp64"][0]["C_f64"]), np.diag(res["fp64"][0]["C_f64"]))))
+    d = np.abs(res["split"][0]["C_f64"] - res["fp64"][0]["C_f64"]) / scale
+    assert np.max(d[1:, 1:]) <= 1e-13, np.max(d[1:, 1:])
+    st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(p - 1)], [True] + [False] * (p - 1))
+    ref = oracle.finalize(st, mask=range(1, p))
+    assert corr_scaled_err(res["split"][1]["cov"], ref["cov"]) <= 1e-12
+    check_final_against_oracle(res["split"][1], ref, [False] * (p - 1), tol=1e-12)
+
+
 @pytest.mark.parametrize("p", [17, 24, 31])
 @pytest.mark.parametrize("n", [1, 63, 4097, 50_001])
 def test_fp64_rows_of_256_bytes_on_matrix_cores(p, n):
