@@ -207,31 +207,60 @@ def run_share(args, L, torch, datagen):
     strides = [4] * 8 + [8, 4]
     itemsz = [4] * 8 + [8, 4]
     host = None
-    if args.host_staged:
-        # pinned host copy of the same rows; the copies through the staging
-        # ring are inside the timed region (PCIe-inclusive rate)
-        log("copying the rows to pinned host memory")
+    chunks = [(off, min(CH, N - off)) for off in range(0, N, CH)]
+    if args.host_staged or args.host_pageable:
+        # a host copy of the same rows; the copies through the staging ring
+        # are inside the timed region (PCIe-inclusive rate).  Pinned: one
+        # page-locked piece per chunk and plane (the rows stream from them
+        # chunk by chunk; one 88 GB page-locked allocation is refused).
+        # Pageable: whole planes in ordinary memory, copied into the two
+        # pinned staging slots by host threads.
+        log("copying the rows to " + ("pageable" if args.host_pageable else "pinned") + " host memory")
         tg = time.perf_counter()
-        host = [torch.empty(N, dtype=dt, pin_memory=True) for dt in dts]
-        for hp, dp in zip(host, planes):
-            hp.copy_(dp)
+        if args.host_pageable:
+            host = [torch.empty(N, dtype=dt) for dt in dts]
+            for hp, dp in zip(host, planes):
+                hp.copy_(dp)
+            bases = [p.data_ptr() for p in host]
+            kind = L.STATS_MEM_HOST
+        else:
+            host = []
+            for off, m in chunks:
+                try:
+                    piece = [torch.empty(m, dtype=dt, pin_memory=True) for dt in dts]
+                except Exception as e:  # page-locked memory exhausted
+                    log(f"page-locking stopped after {off} rows ({off * bpr / 1e9:.1f} GB): {str(e)[:60]}")
+                    break
+                for hp, dp in zip(piece, planes):
+                    hp.copy_(dp[off:off + m])
+                host.append(piece)
+            if not host:
+                raise RuntimeError("no chunk could be page-locked; use --host-pageable")
+            # stream the whole chunks that could be page-locked
+            chunks = chunks[:len(host)]
+            N = sum(m for _, m in chunks)
+            bases = None
+            kind = L.STATS_MEM_HOST_PINNED
+        torch.cuda.synchronize()
         gen_s = time.perf_counter() - tg
         del planes
         torch.cuda.empty_cache()
-        bases = [p.data_ptr() for p in host]
-        kind = L.STATS_MEM_HOST_PINNED
     else:
         bases = [p.data_ptr() for p in planes]
         kind = L.STATS_MEM_DEVICE
     cfg = L.make_config(cols, strides, stream=stream, timing=True, staging_rows=CH)
     h = L.stats_open(cfg)
-    chunks = [(off, min(CH, N - off)) for off in range(0, N, CH)]
 
     def step():
         L.stats_reset(h)
         if kind == L.STATS_MEM_DEVICE:
             for off, m in chunks:
                 L.stats_accumulate(h, [b + off * s for b, s in zip(bases, itemsz)], m)
+        elif kind == L.STATS_MEM_HOST_PINNED:
+            # one call per chunk: the ring's slots and events persist across
+            # calls, so the copy of chunk k + 1 still overlaps the reduction of k
+            for (off, m), piece in zip(chunks, host):
+                L.stats_accumulate(h, [p.data_ptr() for p in piece], m, kind)
         else:
             L.stats_accumulate(h, bases, N, kind)
         return L.stats_finalize(h, 10)
@@ -282,7 +311,8 @@ def run_share(args, L, torch, datagen):
     L.stats_close(h)
     out = base_json(args, rows_per_s, "rows/s", ms_per_step, "f64",
                     {"workload": ("table1_share_2e9_rows" if N == 2_000_000_000 else f"table1_{N}_rows") +
-                     "_int32x9_fp64_" + ("pinned_host" if host is not None else "hbm"),
+                     "_int32x9_fp64_" + ("hbm" if host is None else
+                                         "pageable_host" if args.host_pageable else "pinned_host"),
                      "rows": N, "p": 10, "chunk_rows": CH, "bytes_per_row": bpr,
                      "step": "reset + accumulate all chunks + finalize (cov, corr, PCA)"})
     out["hbm_gbs_end_to_end"] = round(N * args.steps * bpr / elapsed / 1e9, 1)
@@ -650,7 +680,10 @@ def main():
     ap.add_argument("--wave-rows", type=int, default=600_000_000)
     ap.add_argument("--cpu-sample-rows", type=int, default=1 << 27)
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--host-staged", action="store_true")
+    ap.add_argument("--host-staged", action="store_true",
+                    help="share: rows streamed from pinned host memory")
+    ap.add_argument("--host-pageable", action="store_true",
+                    help="share: rows streamed from pageable host memory")
     ap.add_argument("--calibrate-copy", action="store_true")
     ap.add_argument("--wide-prefix-rows", type=int, default=1 << 18,
                     help="wide: rows the oracle reduces for cpu_baseline and the error check")

@@ -521,7 +521,7 @@ int accumulate_device(stats_ctx* h, const void* const* planes, int64_t nrows) {
 
 // Host input: chunks of staging_rows rows go through two device slots; the
 // copy of chunk k+1 (copy stream) overlaps the reduction of chunk k.
-// Pageable input is first copied into two pinned host slots by the CPU.
+// Pageable input is first copied into two pinned host slots by host threads.
 // Fills `bytes` bytes at dst from the file at byte offset off with positioned
 // reads split over up to kReaders host threads.  false on a read error or end
 // of file.
@@ -549,6 +549,21 @@ static bool read_file_range(int fd, char* dst, size_t bytes, int64_t off) {
   for (int k = 0; k < n; ++k)
     if (!ok[k]) return false;
   return true;
+}
+
+// Copies `bytes` from pageable src to the pinned staging slot dst on up to
+// kReaders host threads (one contiguous piece each).
+static void copy_to_slot(char* dst, const char* src, size_t bytes) {
+  const size_t piece = std::max<size_t>((size_t)1 << 24, (bytes + kReaders - 1) / kReaders);
+  const int n = (int)std::min<size_t>(kReaders, (bytes + piece - 1) / piece);
+  auto work = [&](int k) {
+    const size_t a = (size_t)k * piece, e = std::min(bytes, a + piece);
+    if (e > a) memcpy(dst + a, src + a, e - a);
+  };
+  std::vector<std::thread> th;
+  for (int k = 1; k < n; ++k) th.emplace_back(work, k);
+  if (n > 0) work(0);
+  for (auto& t : th) t.join();
 }
 
 int accumulate_host(stats_ctx* h, const void* const* planes, int64_t nrows, bool pinned) {
@@ -615,7 +630,7 @@ int accumulate_host_src(stats_ctx* h, const void* const* planes, int fd, int64_t
             return fail(STATS_E_IO, "reading rows " + std::to_string(done) + " .. " +
                                         std::to_string(done + rows) + " of the file failed");
         } else {
-          memcpy(hs, src, bytes);
+          copy_to_slot(hs, src, bytes);
         }
         src = hs;
       }
