@@ -72,6 +72,20 @@ def traffic_from_profile(units_per_launch, workload="share"):
     return d["hbm_bytes_per_unit"] * units_per_launch
 
 
+def frac_from_kernel_trace():
+    """The accumulate kernel's fraction of peak from the committed
+    rocprofv3 kernel trace of the share workload, or None when absent or
+    taken on a different kernel source."""
+    try:
+        with open(os.path.join(ROOT, "profiles", "accum_small_p_table1_2e9_kernel_trace.json")) as f:
+            d = json.load(f)
+    except (OSError, ValueError):
+        return None
+    if d.get("kernel_source_sha") != kernel_sha("share"):
+        return None
+    return round(d["frac_of_8000_gbs"], 4)
+
+
 def calibrate_copy(torch):
     """A plain 1 GiB device-to-device copy (reads 1 GiB, writes 1 GiB): its
     FETCH_SIZE / WRITE_SIZE readings scale the counters to bytes."""
@@ -289,6 +303,8 @@ def run_share(args, L, torch, datagen):
     rows_per_launch = N * args.steps / max(launches, 1)
     roof = hbm_roofline("accum_small_p (p=10, int32x9 + fp64 planes)", N * args.steps * bpr, ms1 - ms0,
                         launches, rows_per_launch * bpr, traffic_from_profile(rows_per_launch, "share"))
+    if N == 2_000_000_000 and CH == 1 << 28:
+        roof["frac_kernel_trace"] = frac_from_kernel_trace()
     if kind == L.STATS_MEM_DEVICE:
         add_measured_read(roof, L, bases, [N * s for s in itemsz], stream)
     log(f"step {ms_per_step:.2f} ms, {rows_per_s:.3e} rows/s, kernel {roof['achieved']:.0f} GB/s")

@@ -37,8 +37,8 @@ constexpr int kThreads = 256;
 constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
 constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = SEG / 256;  // bytes of line starts per thread (one slice per thread)
-constexpr int MAXLS = 4096;      // line starts per workgroup kept in the table
-constexpr int STAGE = 16 + SEG + MAXLINE;
+constexpr int MAXLS = 2048;      // line starts per workgroup kept in the table
+constexpr int STAGE = 32 + SEG + MAXLINE;  // + up to 15 bytes of alignment in front
 constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 2) * 16;  // room for word reads past the end
 
 struct Args {
@@ -394,16 +394,146 @@ __device__ __attribute__((noinline)) Parsed parse_wide(Stage S, int f, bool is_i
   return out;
 }
 
-// Parses the line starting at L (p fields) into row[0..p).  Returns the
-// position of its end ('\n' or nend), or -1 - end on a malformed line
-// (*bad_at = the offending field's offset).
-__device__ inline int parse_line(const Args& a, Cur& C, int L, uint64_t* row, int* bad_at) {
+// ---- fast path for the common field forms -----------------------------------
+//
+// Bytes [pos, pos + 20) of the staged text in five words (first character in
+// the low byte of w[0]); positions at or past lim read as 0xFF.  pos <= lim,
+// so every word read lies inside the staging buffer.
+__device__ inline void window20(const Cur& C, int pos, uint32_t (&w)[5]) {
+  const __attribute__((address_space(3))) unsigned char* b =
+      (const __attribute__((address_space(3))) unsigned char*)C.S->s;
+  const int a = pos & ~3;
+  uint32_t r[6];
+#pragma unroll
+  for (int j = 0; j < 6; ++j) r[j] = *(const __attribute__((address_space(3))) uint32_t*)(b + pad(a + 4 * j));
+  const uint32_t sh = (uint32_t)(pos & 3);
+#pragma unroll
+  for (int j = 0; j < 5; ++j) w[j] = __builtin_amdgcn_alignbyte(r[j + 1], r[j], sh);
+  const int room = C.S->lim - pos;
+  if (room < 20) {
+#pragma unroll
+    for (int j = 0; j < 5; ++j) {
+      const int rj = room - 4 * j;
+      w[j] |= rj <= 0 ? 0xFFFFFFFFu : (rj < 4 ? (0xFFFFFFFFu << (8 * rj)) : 0u);
+    }
+  }
+}
+
+__device__ inline uint32_t pow10_upto4(int k) {  // 10^k, 0 <= k <= 4
+  return k >= 2 ? (k == 4 ? 10000u : (k == 3 ? 1000u : 100u)) : (k == 1 ? 10u : 1u);
+}
+
+// The leading decimal digits of the 4 NW bytes w[0..NW-1]: their count k
+// (0..4 NW), appended to *val (*val = *val 10^k + their value; wraps modulo
+// 2^64, which only matters past 19 digits), four digits per step (the SWAR
+// step of digit_run).  A lane stops at its first word that is not all digits.
+template <int NW>
+__device__ inline int lead_digits(const uint32_t (&w)[5], uint64_t* val) {
+  uint64_t v = *val;
+  int k = 0;
+#pragma unroll
+  for (int j = 0; j < NW; ++j) {
+    const uint32_t x = w[j];
+    const uint32_t m = ((x & 0xF0F0F0F0u) ^ 0x30303030u) | (((x & 0x0F0F0F0Fu) + 0x06060606u) & 0xF0F0F0F0u);
+    const int kj = m ? (__builtin_ctz(m) >> 3) : 4;
+    const uint32_t y = kj ? (x & 0x0F0F0F0Fu) << (8 * (4 - kj)) : 0u;
+    const uint32_t t = y * 10u + (y >> 8);
+    v = v * pow10_upto4(kj) + ((t & 0xFFu) * 100u + ((t >> 16) & 0xFFu));
+    k += kj;
+    if (kj < 4) break;
+  }
+  *val = v;
+  return k;
+}
+
+// Byte k (0 <= k < 20) of w[0..4].
+__device__ inline uint32_t byte_at(const uint32_t (&w)[5], int k) {
+  const int j = k >> 2;
+  const uint32_t x = j >= 2 ? (j >= 4 ? w[4] : (j == 3 ? w[3] : w[2])) : (j == 1 ? w[1] : w[0]);
+  return (x >> (8 * (k & 3))) & 0xFFu;
+}
+
+// The field at f when it has one of the common forms: [sign] 1..15 digits
+// (integer columns), or [sign] digits [. digits] with 1..19 digits in all and
+// no exponent (decimal columns).  Then it returns true with the terminator's
+// position in *end, its byte in *term (-1 past the text) and the value bits in
+// *bits, exactly as parse_field gives them (the same w, digit count and q go
+// to decimal_value); otherwise false, and parse_field takes the field.
+__device__ inline bool fast_field(const Cur& C, int f, bool is_int, int* end, int* term, uint64_t* bits) {
+  uint32_t w[5];
+  window20(C, f, w);
+  const uint32_t c0 = w[0] & 0xFFu;
+  const bool neg = c0 == '-';
+  const int sg = (c0 == '-' || c0 == '+') ? 1 : 0;
+  if (sg) {
+#pragma unroll
+    for (int j = 0; j < 4; ++j) w[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], 1u);
+  }
+  uint64_t v = 0;
+  const int k1 = lead_digits<4>(w, &v);
+  if (k1 > 15) return false;
+  int p = f + sg + k1;  // the byte after the digits
+  int c = p >= C.S->lim ? -1 : (int)byte_at(w, k1);
+  int nd = k1, q = 0;
+  if (!is_int && c == '.') {
+    // fraction digits appended to v: w = (integer digits)(fraction digits)
+    int k2 = 0;
+    ++p;
+    if (p < C.S->lim) {
+      uint32_t w2[5];
+      window20(C, p, w2);
+      k2 = lead_digits<5>(w2, &v);
+      if (k1 + k2 > 19) return false;
+      c = p + k2 >= C.S->lim ? -1 : (int)byte_at(w2, k2);
+    } else {
+      c = -1;
+    }
+    nd = k1 + k2;
+    q = -k2;
+    p += k2;
+  }
+  if (nd == 0 || (c != ',' && c != '\n' && c != -1)) return false;
+  if (is_int) {
+    const int64_t x = (int64_t)v;
+    *bits = (uint64_t)(neg ? -x : x);
+  } else {
+    bool bad = false;
+    const double d = decimal_value((u128)v, nd, q, false, neg, &bad);
+    if (bad) return false;
+    *bits = (uint64_t)__double_as_longlong(d);
+  }
+  *end = p;
+  *term = c;
+  return true;
+}
+
+// parse_field out of line, for the fields fast_field does not take.
+__device__ __attribute__((noinline)) Parsed slow_field(Stage S, int f, bool is_int) {
+  Cur C(S);
+  uint64_t bits = 0;
+  const int r = parse_field(C, f, is_int, &bits);
+  return Parsed{r, bits};
+}
+
+// Parses the line starting at L (P fields) into row[0..P), each field through
+// fast_field first, else parse_field.  Returns the position of its end ('\n'
+// or nend), or -1 - end on a malformed line (*bad_at = the offending field's
+// offset).
+template <int P>
+__device__ inline int parse_line_p(const Args& a, Cur& C, int L, uint64_t (&row)[P], int* bad_at) {
   int f = L;
-  for (int c = 0; c < a.p; ++c) {
+#pragma unroll
+  for (int c = 0; c < P; ++c) {
+    const bool is_int = (a.intmask >> c) & 1u;
     uint64_t bits = 0;
-    const int r = parse_field(C, f, (a.intmask >> c) & 1u, &bits);
-    const bool last = c == a.p - 1;
-    const int term = r >= 0 ? C.at(r) : 0;
+    int r, term;
+    if (!fast_field(C, f, is_int, &r, &term, &bits)) {
+      const Parsed sp = slow_field(*C.S, f, is_int);
+      r = sp.pos;
+      bits = sp.bits;
+      term = r >= 0 ? C.at(r) : 0;
+    }
+    const bool last = c == P - 1;
     const bool ok = r >= 0 && (last ? (term == '\n' || term == -1) : term == ',');
     if (!ok) {
       *bad_at = f;
@@ -422,27 +552,45 @@ __device__ inline int parse_line(const Args& a, Cur& C, int L, uint64_t* row, in
   return f;
 }
 
-// Copies the text [w0, w0 + n) of buf into LDS (padded 16 bytes per 256):
-// aligned 16-byte loads in the middle, single bytes at the two ragged ends,
-// so that no byte outside [buf + w0, buf + w0 + n) is read.
-__device__ inline void stage_text(const char* buf, int64_t w0, int n, unsigned char* s_buf) {
-  const uintptr_t lo = (uintptr_t)(buf + w0), hi = (uintptr_t)(buf + w0 + n);
-  const uintptr_t alo = (lo + 15) & ~(uintptr_t)15, ahi = hi & ~(uintptr_t)15;
-  if (alo < ahi) {
-    const int head = (int)(alo - lo);
-    const int nvec = (int)((ahi - alo) / 16);
-    for (int v = threadIdx.x; v < nvec; v += kThreads) {
-      const uint4 qv = *(const uint4*)(alo + 16 * (uintptr_t)v);
-      const unsigned char* qb = (const unsigned char*)&qv;
+// Copies the text [w0r, w0r + nr) of buf into LDS (padded 16 bytes per 256)
+// on a 16-byte aligned origin: LDS position i holds stream byte w0r - sh + i,
+// sh = the misalignment of buf + w0r, which is returned.  Every thread issues
+// its aligned 16-byte loads before its first LDS write; the vectors at the
+// two ends are assembled byte by byte so that nothing outside
+// [buf + w0r - (w0r >= 16 ? sh : 0), buf + w0r + nr) is read (positions before
+// w0r hold zeros when w0r < 16, earlier stream bytes otherwise).
+__device__ inline int stage_text(const char* buf, int64_t w0r, int nr, unsigned char* s_buf) {
+  const int sh = (int)((uintptr_t)(buf + w0r) & 15u);
+  const char* base = buf + w0r - sh;
+  const int tot = sh + nr;
+  const int nv = (tot + 15) >> 4;
+  constexpr int NVT = (STAGE + 15) / 16 / kThreads + 1;
+  u32x4 q[NVT];
 #pragma unroll
-      for (int k = 0; k < 16; ++k) s_buf[pad(head + 16 * v + k)] = qb[k];
+  for (int u = 0; u < NVT; ++u) {
+    const int v = (int)threadIdx.x + u * kThreads;
+    q[u] = (u32x4){0u, 0u, 0u, 0u};
+    if (v < nv) {
+      const int p0 = 16 * v;
+      if (p0 + 16 <= tot && (w0r >= 16 || p0 >= sh)) {
+        q[u] = *(const u32x4*)(base + p0);
+      } else {
+        uint32_t wd[4] = {0u, 0u, 0u, 0u};
+        for (int k = 0; k < 16; ++k) {
+          const int pos = p0 + k;
+          if (pos >= sh && pos < tot)
+            wd[k >> 2] |= (uint32_t)(unsigned char)buf[w0r + pos - sh] << (8 * (k & 3));
+        }
+        q[u] = (u32x4){wd[0], wd[1], wd[2], wd[3]};
+      }
     }
-    for (int k = threadIdx.x; k < head; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
-    const int tail0 = head + 16 * nvec;
-    for (int k = tail0 + threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
-  } else {
-    for (int k = threadIdx.x; k < n; k += kThreads) s_buf[pad(k)] = (unsigned char)buf[w0 + k];
   }
+#pragma unroll
+  for (int u = 0; u < NVT; ++u) {
+    const int v = (int)threadIdx.x + u * kThreads;
+    if (v < nv) *(__attribute__((address_space(3))) u32x4*)(s_buf + pad(16 * v)) = q[u];
+  }
+  return sh;
 }
 
 // Line starts of a workgroup's segment [s0r, s1r) (stage-relative; a line
@@ -529,117 +677,175 @@ __device__ inline int line_starts(const unsigned char* s_buf, int64_t w0, int s0
   return total;
 }
 
+typedef double d4 __attribute__((ext_vector_type(4)));
+
+// Waits for this wave's LDS accesses; also keeps the compiler from moving
+// LDS accesses across it (the rows a wave stages are read by other lanes).
+__device__ inline void wave_lds_sync() { asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory"); }
+
+// Products on the FP64 matrix cores: each wave stages the shifted rows of its
+// lanes' lines, 32 at a time, in its own LDS rows; for v_mfma_f64_16x16x4f64
+// a lane then holds column (lane % 16) of staged row 4 m + lane / 16, at once
+// its element of the A operand (column i, row k) and of the B operand (row k,
+// column j), so 8 products give the 32 rows' upper triangle; absent or
+// malformed lines stage zeros.  The column sums are kept per lane.  For
+// integer columns every partial sum is an integer below 2^53 under the guard
+// checked by the merge, so the matrix-core sums are exact; the order of all
+// sums is fixed, so results are bitwise reproducible.
 template <int P>
-__global__ __launch_bounds__(kThreads, (P <= 10 ? 2 : 1)) void k_text(Args a) {
+__global__ __launch_bounds__(kThreads, 2) void k_text(Args a) {
+  constexpr int T = P * (P + 1) / 2;
+  constexpr int NWV = kThreads / 64;
   __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
-  __shared__ uint64_t s_row[kThreads][P];
+  __shared__ uint64_t s_rows[NWV][32 * P];  // per wave: 32 staged rows (raw field bits)
+  __shared__ int s_valid[NWV][32];
   __shared__ uint64_t sKb[P];
   __shared__ unsigned long long s_n;
   __shared__ unsigned short s_ls[MAXLS];  // line starts (stage-relative)
-  __shared__ int s_wsum[kThreads / 64];
+  __shared__ int s_wsum[NWV];
+  static_assert(STAGE_PADDED >= NWV * 5 * 64 * 8, "the final reduction reuses the text stage");
   const int64_t s0 = (int64_t)blockIdx.x * SEG;
   const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
-  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
+  const int64_t w0r = s0 >= 16 ? s0 - 16 : 0;  // first stream byte staged
   const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
+  // w0: stream offset of LDS position 0 (the staging origin is aligned)
+  const int64_t w0 = w0r - stage_text(a.buf, w0r, (int)(w1 - w0r), s_buf);
   const int n = (int)(w1 - w0);
-  stage_text(a.buf, w0, n, s_buf);
   if (threadIdx.x == 0) s_n = 0;
   __syncthreads();
   const Stage S{s_buf, w0, n, (int)(min(a.nend, w0 + (int64_t)n) - w0)};
   const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);  // relative positions
-
-  // shift words (int64 for integer columns, FP64 bits otherwise): the row of
-  // the workgroup's first line, zeros if it does not parse; set below
-  uint64_t K64[P];
-#pragma unroll
-  for (int c = 0; c < P; ++c) K64[c] = 0;
-
-  acc::Acc<P> A;
-  A.zero();
-  uint32_t bad = 0;
-  unsigned long long nrows = 0;
-  int first_bad = INT32_MAX;
   Cur C(S);
-  auto add_row = [&](const uint64_t* row) {
-    double d[P];
-#pragma unroll
-    for (int c = 0; c < P; ++c) {
-      const uint64_t b = row[c];
-      d[c] = ((a.intmask >> c) & 1u) ? (double)((int64_t)b - (int64_t)K64[c])
-                                      : __longlong_as_double((long long)b) - __longlong_as_double((long long)K64[c]);
-    }
-    A.add(d);
-    ++nrows;
-  };
-  auto take_line = [&](int L) -> int {  // parses and accumulates one line; returns the next position
-    uint64_t* row = s_row[threadIdx.x];
-    int bad_at = INT32_MAX;
-    const int end = parse_line(a, C, L, row, &bad_at);
-    if (end >= 0) {
-      add_row(row);
-      return end + 1;
-    }
-    first_bad = min(first_bad, bad_at);
-    return (-1 - end) + 1;
-  };
 
-  // line starts in [s0, s1); thread t then parses lines t, t + 256, ...: the
-  // lanes of a wave walk the same fields of different lines side by side
   int c0, c1, before;
   const int total = line_starts(s_buf, w0, s0r, s1r, s_ls, s_wsum, &c0, &c1, &before);
   (void)before;
-  if (total <= MAXLS) {
-    // the first pass (lines 0..255) parses only; line 0 is the workgroup's
-    // first line, whose row (copied by thread 0 before the barrier) is the
-    // block shift
-    int end0 = -1, bad0 = INT32_MAX;
-    uint64_t* row0 = s_row[threadIdx.x];
-    if ((int)threadIdx.x < total) end0 = parse_line(a, C, (int)s_ls[threadIdx.x], row0, &bad0);
-    if (threadIdx.x == 0)
-      for (int c = 0; c < P; ++c) sKb[c] = end0 >= 0 ? row0[c] : 0;
-    __syncthreads();
-#pragma unroll
-    for (int c = 0; c < P; ++c) K64[c] = sKb[c];
-    if ((int)threadIdx.x < total) {
-      if (end0 >= 0) add_row(row0);
-      else first_bad = min(first_bad, bad0);
+  const bool table = total <= MAXLS;
+
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int col = lane & 15, rsub = lane >> 4;
+  uint64_t* wr = s_rows[wave];
+  int* wv = s_valid[wave];
+  d4 acc = {0.0, 0.0, 0.0, 0.0}, acc2 = {0.0, 0.0, 0.0, 0.0};  // even and odd steps
+  double colsum = 0.0;
+  unsigned long long nrows = 0;
+  int first_bad = INT32_MAX;
+  // this lane's column of the products and its shift
+  const bool colv = col < P;
+  const bool colint = colv && ((a.intmask >> col) & 1u);
+  double Kc = 0.0;
+  int64_t Kic = 0;
+  // this lane's lines: table entries threadIdx.x, + 256, ...; or, when the
+  // table overflowed, the lines starting in its own slice
+  int idx = threadIdx.x;
+  int Lc = c0;
+  if (!table && w0 + Lc > 0)
+    while (Lc < c1 && C.at(Lc - 1) != '\n') ++Lc;
+  for (int round = 0;; ++round) {
+    bool have;
+    int L;
+    if (table) {
+      have = idx < total;
+      L = have ? (int)s_ls[idx] : 0;
+      idx += kThreads;
+    } else {
+      have = Lc < c1;
+      L = Lc;
     }
-    for (int k = threadIdx.x + kThreads; k < total; k += kThreads) (void)take_line((int)s_ls[k]);
-  } else {
-    // too many lines for the table: the shift from the first line, found by
-    // one thread, then each thread walks its own slice
-    if (threadIdx.x == 0) {
-      int L = s0r;
-      if (s0 > 0)
-        while (L < s1r && C.at(L - 1) != '\n') ++L;
-      int bad_at;
-      if (L >= s1r || parse_line(a, C, L, s_row[0], &bad_at) < 0)
-        for (int c = 0; c < P; ++c) s_row[0][c] = 0;
-      for (int c = 0; c < P; ++c) sKb[c] = s_row[0][c];
+    // every wave runs round 0 (its barrier); later rounds while a lane has a line
+    if (round > 0 && __builtin_amdgcn_ballot_w64(have) == 0) break;
+    uint64_t row[P];
+    bool ok = false;
+    if (have) {
+      int bad_at = INT32_MAX;
+      const int end = parse_line_p<P>(a, C, L, row, &bad_at);
+      ok = end >= 0;
+      if (ok) {
+        ++nrows;
+        Lc = end + 1;
+      } else {
+        first_bad = min(first_bad, bad_at);
+        Lc = (-1 - end) + 1;
+      }
     }
-    __syncthreads();
+    if (round == 0) {
+      // block shift: the row of thread 0's first line (the workgroup's first
+      // line when the table holds them all), zeros if it does not parse
+      if (threadIdx.x == 0) {
 #pragma unroll
-    for (int c = 0; c < P; ++c) K64[c] = sKb[c];
-    int L = c0;
-    if (w0 + L > 0)
-      while (L < c1 && C.at(L - 1) != '\n') ++L;
-    while (L < c1) L = take_line(L);
+        for (int c = 0; c < P; ++c) sKb[c] = ok ? row[c] : 0;
+      }
+      __syncthreads();
+      const uint64_t kb = colv ? sKb[col] : 0;
+      Kic = colint ? (int64_t)kb : 0;
+      Kc = colint ? (double)Kic : __longlong_as_double((long long)kb);
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      if ((lane >> 5) == h) {
+        if (ok) {
+#pragma unroll
+          for (int c = 0; c < P; ++c) wr[(lane & 31) * P + c] = row[c];
+        }
+        wv[lane & 31] = ok;
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int m = 0; m < 8; ++m) {
+        const int sr = 4 * m + rsub;
+        double v = 0.0;
+        if (colv && wv[sr]) {
+          const uint64_t b = wr[sr * P + col];
+          v = colint ? (double)((int64_t)b - Kic) : __longlong_as_double((long long)b) - Kc;
+        }
+        colsum += v;
+        if (m & 1) acc2 = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc2, 0, 0, 0);
+        else acc = __builtin_amdgcn_mfma_f64_16x16x4f64(v, v, acc, 0, 0, 0);
+      }
+      wave_lds_sync();
+    }
   }
   if (first_bad != INT32_MAX) {
     atomicMin(&a.status->parse_off, (unsigned long long)(a.base_off + w0 + first_bad));
     atomicOr(&a.status->bits, ST_PARSE);
   }
   atomicAdd(&s_n, nrows);
-  __syncthreads();
-  double K[P];
-  int64_t Ki[P];
+  __syncthreads();  // the text stage is free: it holds the per-wave sums now
+  double* red = (double*)s_buf;  // [wave][4 registers + 1 sum][64 lanes]
 #pragma unroll
-  for (int c = 0; c < P; ++c) {
-    const bool ic = (a.intmask >> c) & 1u;
-    Ki[c] = ic ? (int64_t)K64[c] : 0;
-    K[c] = ic ? (double)Ki[c] : __longlong_as_double((long long)K64[c]);
+  for (int r = 0; r < 4; ++r) red[(wave * 5 + r) * 64 + lane] = acc[r] + acc2[r];
+  red[(wave * 5 + 4) * 64 + lane] = colsum;
+  __syncthreads();
+  const acc::Args& ra = a.acc;
+  uint64_t* out = ra.rec + (int64_t)blockIdx.x * (2 + 2 * P + T);
+  for (int e = threadIdx.x; e < 4 * 64; e += kThreads) {
+    // register r of lane l holds D[4r + l/16][l%16]
+    const int r = e >> 6, l = e & 63;
+    const int i = 4 * r + (l >> 4), j = l & 15;
+    if (i <= j && j < P) {
+      double v = red[r * 64 + l];
+#pragma unroll
+      for (int w = 1; w < NWV; ++w) v += red[(w * 5 + r) * 64 + l];
+      const int t = i * P - i * (i - 1) / 2 + (j - i);
+      out[2 + P + ra.dst[P + t]] = (uint64_t)__double_as_longlong(v);
+    }
   }
-  acc::finish_block<P>(a.acc, A, K, Ki, bad, 0, (int64_t)s_n);
+  if (threadIdx.x < P) {
+    const int c = threadIdx.x;
+    double v = 0.0;
+#pragma unroll
+    for (int w = 0; w < NWV; ++w)
+#pragma unroll
+      for (int k = 0; k < 4; ++k) v += red[(w * 5 + 4) * 64 + c + 16 * k];
+    out[2 + P + ra.dst[c]] = (uint64_t)__double_as_longlong(v);
+    // the shift word: the int64 value for integer columns, FP64 bits
+    // otherwise, i.e. sKb as parsed
+    out[2 + ra.kdst[c]] = sKb[c];
+  }
+  if (threadIdx.x == 0) {
+    out[0] = (uint64_t)s_n;
+    out[1] = 0;
+  }
 }
 
 // Position after the last '\n' in [0, n), or 0 when there is none; one
@@ -744,16 +950,16 @@ __device__ inline bool store_field(const ConvArgs& a, int c, int64_t r, uint64_t
 template <int P>
 __global__ __launch_bounds__(kThreads) void k_text_convert(ConvArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char s_buf[STAGE_PADDED];
-  __shared__ uint64_t s_row[kThreads][P];
   __shared__ unsigned short s_ls[MAXLS];
   __shared__ int s_wsum[kThreads / 64];
   const Args& t = a.t;
   const int64_t s0 = (int64_t)blockIdx.x * SEG;
   const int64_t s1 = min(s0 + (int64_t)SEG, t.nend);
-  const int64_t w0 = s0 >= 16 ? s0 - 16 : 0;
+  const int64_t w0r = s0 >= 16 ? s0 - 16 : 0;  // first stream byte staged
   const int64_t w1 = min(s1 + (int64_t)MAXLINE, t.nbytes);
+  // w0: stream offset of LDS position 0 (the staging origin is aligned)
+  const int64_t w0 = w0r - stage_text(t.buf, w0r, (int)(w1 - w0r), s_buf);
   const int n = (int)(w1 - w0);
-  stage_text(t.buf, w0, n, s_buf);
   __syncthreads();
   const Stage S{s_buf, w0, n, (int)(min(t.nend, w0 + (int64_t)n) - w0)};
   const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);
@@ -764,9 +970,9 @@ __global__ __launch_bounds__(kThreads) void k_text_convert(ConvArgs a) {
   int first_bad = INT32_MAX;
   // parses line L (k-th of the segment) into output row base + k
   auto put_line = [&](int L, int k) -> int {
-    uint64_t* row = s_row[threadIdx.x];
+    uint64_t row[P];
     int bad_at = INT32_MAX;
-    const int end = parse_line(t, C, L, row, &bad_at);
+    const int end = parse_line_p<P>(t, C, L, row, &bad_at);
     if (end < 0) {
       first_bad = min(first_bad, L);  // reported by the line's first byte
       return -end;  // (-1 - e) + 1: past the offending line
