@@ -419,38 +419,38 @@ __device__ inline void window20(const Cur& C, int pos, uint32_t (&w)[5]) {
   }
 }
 
-__device__ inline uint32_t pow10_upto4(int k) {  // 10^k, 0 <= k <= 4
-  return k >= 2 ? (k == 4 ? 10000u : (k == 3 ? 1000u : 100u)) : (k == 1 ? 10u : 1u);
+__device__ inline uint32_t pow10_upto4(int k) {  // 10^k, 0 <= k <= 4, without branches
+  return k == 4 ? 10000u : (uint32_t)(0x03E80064000A0001ull >> (16 * k)) & 0xFFFFu;
 }
 
 // The leading decimal digits of the 4 NW bytes w[0..NW-1]: their count k
 // (0..4 NW), appended to *val (*val = *val 10^k + their value; wraps modulo
-// 2^64, which only matters past 19 digits), four digits per step (the SWAR
-// step of digit_run).  A lane stops at its first word that is not all digits.
+// 2^64, which only matters past 19 digits), and the byte after them in *term
+// (0xFF when all 4 NW bytes are digits).  Four digits per step (the SWAR step
+// of digit_run); the steps stop when no lane of the wave has digits left.
 template <int NW>
-__device__ inline int lead_digits(const uint32_t (&w)[5], uint64_t* val) {
+__device__ inline int lead_digits(const uint32_t (&w)[5], uint64_t* val, uint32_t* term) {
   uint64_t v = *val;
   int k = 0;
+  bool done = false;
+  uint32_t t8 = 0xFFu;
 #pragma unroll
   for (int j = 0; j < NW; ++j) {
+    if (j > 0 && __builtin_amdgcn_ballot_w64(!done) == 0) break;  // wave-uniform
     const uint32_t x = w[j];
     const uint32_t m = ((x & 0xF0F0F0F0u) ^ 0x30303030u) | (((x & 0x0F0F0F0Fu) + 0x06060606u) & 0xF0F0F0F0u);
-    const int kj = m ? (__builtin_ctz(m) >> 3) : 4;
+    const int kw = m ? (__builtin_ctz(m) >> 3) : 4;
+    const int kj = done ? 0 : kw;
     const uint32_t y = kj ? (x & 0x0F0F0F0Fu) << (8 * (4 - kj)) : 0u;
     const uint32_t t = y * 10u + (y >> 8);
     v = v * pow10_upto4(kj) + ((t & 0xFFu) * 100u + ((t >> 16) & 0xFFu));
+    if (!done && kw < 4) t8 = (x >> (8 * kw)) & 0xFFu;
     k += kj;
-    if (kj < 4) break;
+    done |= kw < 4;
   }
   *val = v;
+  *term = t8;
   return k;
-}
-
-// Byte k (0 <= k < 20) of w[0..4].
-__device__ inline uint32_t byte_at(const uint32_t (&w)[5], int k) {
-  const int j = k >> 2;
-  const uint32_t x = j >= 2 ? (j >= 4 ? w[4] : (j == 3 ? w[3] : w[2])) : (j == 1 ? w[1] : w[0]);
-  return (x >> (8 * (k & 3))) & 0xFFu;
 }
 
 // The field at f when it has one of the common forms: [sign] 1..15 digits
@@ -464,27 +464,26 @@ __device__ inline bool fast_field(const Cur& C, int f, bool is_int, int* end, in
   window20(C, f, w);
   const uint32_t c0 = w[0] & 0xFFu;
   const bool neg = c0 == '-';
-  const int sg = (c0 == '-' || c0 == '+') ? 1 : 0;
-  if (sg) {
+  const uint32_t sg = (c0 == '-' || c0 == '+') ? 1u : 0u;
 #pragma unroll
-    for (int j = 0; j < 4; ++j) w[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], 1u);
-  }
+  for (int j = 0; j < 4; ++j) w[j] = __builtin_amdgcn_alignbyte(w[j + 1], w[j], sg);
   uint64_t v = 0;
-  const int k1 = lead_digits<4>(w, &v);
+  uint32_t t1;
+  const int k1 = lead_digits<4>(w, &v, &t1);
   if (k1 > 15) return false;
-  int p = f + sg + k1;  // the byte after the digits
-  int c = p >= C.S->lim ? -1 : (int)byte_at(w, k1);
+  int p = f + (int)sg + k1;  // the byte after the digits
+  int c = p >= C.S->lim ? -1 : (int)t1;
   int nd = k1, q = 0;
   if (!is_int && c == '.') {
     // fraction digits appended to v: w = (integer digits)(fraction digits)
     int k2 = 0;
     ++p;
     if (p < C.S->lim) {
-      uint32_t w2[5];
+      uint32_t w2[5], t2;
       window20(C, p, w2);
-      k2 = lead_digits<5>(w2, &v);
+      k2 = lead_digits<5>(w2, &v, &t2);
       if (k1 + k2 > 19) return false;
-      c = p + k2 >= C.S->lim ? -1 : (int)byte_at(w2, k2);
+      c = p + k2 >= C.S->lim ? -1 : (int)t2;
     } else {
       c = -1;
     }
