@@ -111,7 +111,8 @@ __global__ __launch_bounds__(kThreads) void k_merge_l2(const uint64_t* __restric
 }
 
 // Records -> state in one pass: one workgroup per entry.  Thread t folds
-// blocks t, t + 256, ... in order, then the 256 partial results are combined
+// blocks t, t + 256, ... in order (the words of eight of them loaded before
+// the first is folded), then the 256 partial results are combined
 // by a fixed binary tree in LDS (Chan update + exact 128-bit sums) and the
 // total is merged into the current state (cur -> next).  The tree shape is
 // fixed, so the result is deterministic.
@@ -136,28 +137,46 @@ __global__ __launch_bounds__(kTreeThreads) void k_merge_tree(const uint64_t* __r
   Chan acc = {0.0, 0.0, 0.0, 0.0};
   i128 exact = 0;
   uint32_t inexact = 0;
-  for (int64_t b = threadIdx.x; b < nblocks; b += kTreeThreads) {
-    const uint64_t* r = rec + b * W;
-    const int64_t nb = (int64_t)r[0];
-    if (nb == 0) continue;
-    const double nbd = (double)nb;
-    const uint64_t Kiw = r[2 + i], Kjw = r[2 + j];
-    const double Si = __longlong_as_double((long long)r[2 + p + i]);
-    const double Sj = __longlong_as_double((long long)r[2 + p + j]);
-    const double Qij = __longlong_as_double((long long)r[2 + 2 * p + t]);
-    Chan blk;
-    blk.n = nbd;
-    blk.mi = kval(Kiw, ii) + Si / nbd;
-    blk.mj = kval(Kjw, ij) + Sj / nbd;
-    blk.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
-    chan_add(acc, blk);
-    if (is_col && ii) {
-      const int64_t K = (int64_t)Kiw;
-      if (r[1] != 0 || !(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
-      exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
-    } else if (!is_col && ii && ij) {
-      const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
-      exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
+  // records b, b + 256, ... in order; the words of kU records are loaded
+  // before the first of them is folded
+  constexpr int kU = 8;
+  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += kTreeThreads * kU) {
+    uint64_t wd[kU][7];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t b = b0 + (int64_t)u * kTreeThreads;
+      const uint64_t* r = rec + (b < nblocks ? b : 0) * W;
+      wd[u][0] = b < nblocks ? r[0] : 0;
+      wd[u][1] = r[1];
+      wd[u][2] = r[2 + i];
+      wd[u][3] = r[2 + j];
+      wd[u][4] = r[2 + p + i];
+      wd[u][5] = r[2 + p + j];
+      wd[u][6] = r[2 + 2 * p + t];
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t nb = (int64_t)wd[u][0];
+      if (nb == 0) continue;
+      const double nbd = (double)nb;
+      const uint64_t Kiw = wd[u][2], Kjw = wd[u][3];
+      const double Si = __longlong_as_double((long long)wd[u][4]);
+      const double Sj = __longlong_as_double((long long)wd[u][5]);
+      const double Qij = __longlong_as_double((long long)wd[u][6]);
+      Chan blk;
+      blk.n = nbd;
+      blk.mi = kval(Kiw, ii) + Si / nbd;
+      blk.mj = kval(Kjw, ij) + Sj / nbd;
+      blk.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
+      chan_add(acc, blk);
+      if (is_col && ii) {
+        const int64_t K = (int64_t)Kiw;
+        if (wd[u][1] != 0 || !(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
+        exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
+      } else if (!is_col && ii && ij) {
+        const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
+        exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
+      }
     }
   }
   if (inexact) atomicOr(&status->bits, ST_INEXACT);
