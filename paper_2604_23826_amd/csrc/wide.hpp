@@ -77,6 +77,8 @@ struct SyrkArgs {
   uint64_t* rec;
   DevStatus* status;
   int* ovf;                 // per block: nonzero = recompute in FP64 (device)
+  const int* sumoffs;       // record words both halves of a diagonal pair add into (device)
+  int nsumoffs;
 };
 
 }  // namespace wide

@@ -390,11 +390,12 @@ struct Ctx {
     }
   }
 
-  // Digits of sub-step t into digit buffer t & 1; with SUMS also the sums
-  // of v, its products with the extras and the checks of limit and
-  // finiteness.
-  template <bool TAIL>
+  // Digits of sub-step t into digit buffer t & 1; with DOSUMS (in a SUMS
+  // workgroup, on the sub-steps of its parity) also the sums of v, its
+  // products with the extras and the checks of grid, limit and finiteness.
+  template <bool TAIL, bool DOSUMS>
   __device__ __attribute__((always_inline)) void digitize(int64_t t, int stage_i, Raw& r, Pending<CPL>& pd) {
+    constexpr bool DS = SUMS && DOSUMS;
     float sc[CPL], nks[CPL], mx[CPL], fs[CPL], fo[CPL];
     int sw[CPL];
 #pragma unroll
@@ -415,7 +416,7 @@ struct Ctx {
     for (int g = 0; g < RW / 4; ++g) {
       uint32_t dw[3][CPL];
       double de[4][NE];
-      if (SUMS && ne > 0) {
+      if (DS && ne > 0) {
         u4 ew[4];
         ex_read(lds(ring) + (uint32_t)(stage_i * STB + RAWB + wave * EXW * 4 + 16 * g), ew);
 #pragma unroll
@@ -443,7 +444,7 @@ struct Ctx {
           if (TAIL) y = (rb + 4 * g + jj < r1) ? y : 0.0f;
           const float fr = y + kRound;
           w[jj] = __float_as_int(fr) + kBias;  // v + 0x8080: bytes d2 + 128, d1 + 128, d0
-          if constexpr (SUMS) {
+          if constexpr (DS) {
             // on the grid: x 2^s is an integer (K is too: it is the first
             // row); the fraction is exact, so this test is too
             float xf = __builtin_amdgcn_fractf(r.x[4 * g + jj][i] * sc[i]);
@@ -476,7 +477,7 @@ struct Ctx {
         else *(u2*)(out + d * 8 * PITCH) = (u2){dw[d][0], dw[d][1]};
       }
     }
-    if constexpr (SUMS) {
+    if constexpr (DS) {
 #pragma unroll
       for (int i = 0; i < CPL; ++i) {
         over |= !(mx[i] <= kVlim) | !(fabsf(fs[i]) <= 3.0e38f) | !(fo[i] == 0.0f);
@@ -682,7 +683,11 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     for (int e = 0; e < NE; ++e) strip[e][i] = 0.0;
   }
   Pending<CPL> pd;
-  auto commit = [&]() {
+  // the sums of sub-step t belong to the half of its parity (both halves of
+  // a diagonal pair are SUMS workgroups; each takes every other sub-step)
+  auto sums_at = [&](int64_t t) { return SUMS && (int)(t & 1) == half; };
+  auto commit = [&](bool now) {
+    if (!now) return;
     if constexpr (SUMS) {
 #pragma unroll
       for (int i = 0; i < CPL; ++i) {
@@ -725,10 +730,15 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   else if (nsub > 1) c.template wait_dma<1>();
   else c.template wait_dma<0>();
   c.fetch(0, raw);
-  if (SR > nrow) c.template digitize<true>(0, 0, raw, pd);
-  else c.template digitize<false>(0, 0, raw, pd);
+  auto digits = [&](int64_t tt, int st, auto tail_c) __attribute__((always_inline)) {
+    constexpr bool TL = decltype(tail_c)::value;
+    if (sums_at(tt)) c.template digitize<TL, true>(tt, st, raw, pd);
+    else c.template digitize<TL, false>(tt, st, raw, pd);
+  };
+  if (SR > nrow) digits(0, 0, std::true_type{});
+  else digits(0, 0, std::false_type{});
   lds_barrier();
-  commit();
+  commit(sums_at(0));
   // Sub-step t: DMA of t + 3 into the stage of t (fetched into registers
   // one sub-step ago), fetch of t + 1 (its DMA was issued two sub-steps
   // ago), products of t, digits of t + 1 (the vector work can fill the
@@ -765,9 +775,9 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
       c.fetch(s_next, raw);
     }
     mma_step<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, L);
-    if constexpr (MORE) c.template digitize<TAIL>(t + 1, s_next, raw, pd);
+    if constexpr (MORE) digits(t + 1, s_next, tail_c);
     lds_barrier();
-    if constexpr (MORE) commit();
+    if constexpr (MORE) commit(sums_at(t + 1));
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
@@ -842,12 +852,15 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
       for (int w = 1; w < NW; ++w) sum += m.red[w * NC + k];
       if (cg < a.F) {
         const int uc = a.col_of[cg];
+        // the two halves' partial sums meet in slots zeroed before the
+        // launch; each part and their sum are exact, so the order of the
+        // two additions does not matter
         if (extra < 0) {
-          out[2 + p + uc] = (uint64_t)__double_as_longlong(sum);
+          atomicAdd((double*)(out + 2 + p + uc), sum);
           out[2 + uc] = (uint64_t)__double_as_longlong((double)m.s_K[k]);
         } else {
           const int ue = a.col_of[a.F + extra];
-          out[2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))] = (uint64_t)__double_as_longlong(sum);
+          atomicAdd((double*)(out + 2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))), sum);
         }
       }
     }
@@ -864,7 +877,7 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
         double s = m.s_ex[e];
         for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + e];
         const int ue = a.col_of[a.F + e];
-        out[2 + p + ue] = (uint64_t)__double_as_longlong(s);
+        atomicAdd((double*)(out + 2 + p + ue), s);
         out[2 + ue] = shift_word(a.ex[e].isint, a.ex[e].kind, m.s_eK[e], m.s_eKi[e]);
       }
       for (int e = 0; e < NE; ++e)
@@ -873,10 +886,12 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
             double s = m.s_ex[NE + tq];
             for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + NE + tq];
             const int ue = a.col_of[a.F + e], uf = a.col_of[a.F + f];
-            out[2 + 2 * p + tri(p, min(ue, uf), max(ue, uf))] = (uint64_t)__double_as_longlong(s);
+            atomicAdd((double*)(out + 2 + 2 * p + tri(p, min(ue, uf), max(ue, uf))), s);
           }
-      out[0] = (uint64_t)nrow;
-      out[1] = 0;
+      if (half == 0) {
+        out[0] = (uint64_t)nrow;
+        out[1] = 0;
+      }
     }
   }
 }
@@ -912,8 +927,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   m.s_ex = s_ex;
   m.s_flag = &s_flag;
   if (A != B) pair_block<false, false>(a, m, b, A, B, half);
-  else if (half == 0) pair_block<true, true>(a, m, b, A, B, 0);
-  else pair_block<true, false>(a, m, b, A, B, 1);
+  else pair_block<true, true>(a, m, b, A, B, half);
 }
 
 __global__ void k_zero_flags(int* f, int64_t n) {
@@ -921,11 +935,21 @@ __global__ void k_zero_flags(int* f, int64_t n) {
   if (i < n) f[i] = 0;
 }
 
+// Zeroes the record words the two halves of a diagonal pair add into: word
+// offs[k] of every record (grid: records x offsets).
+__global__ void k_zero_sum_slots(uint64_t* rec, int64_t W, const int* offs, int noffs, int64_t nrec) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < nrec * noffs) rec[(i / noffs) * W + offs[i % noffs]] = 0;
+}
+
 }  // namespace syrk
 
 void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(syrk::k_zero_flags, dim3((unsigned)((a.nblocks + 255) / 256)), dim3(256), 0, s, a.ovf,
                      a.nblocks);
+  const int64_t nz = a.nblocks * a.nsumoffs;
+  hipLaunchKernelGGL(syrk::k_zero_sum_slots, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, a.rec,
+                     rec_words(a.p), a.sumoffs, a.nsumoffs, a.nblocks);
   const int64_t nb8 = (a.nblocks + 7) / 8 * 8;
   hipLaunchKernelGGL(syrk::k_syrk_i8, dim3((unsigned)(nb8 * a.npairs)), dim3(syrk::kThreads), 0, s, a);
 }
