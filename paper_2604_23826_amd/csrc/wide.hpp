@@ -77,8 +77,7 @@ struct SyrkArgs {
   uint64_t* rec;
   DevStatus* status;
   int* ovf;                 // per block: nonzero = recompute in FP64 (device)
-  const int* sumoffs;       // record words both halves of a diagonal pair add into (device)
-  int nsumoffs;
+  int* sexp;                // grid exponents, nblocks x F (device; written by the matrix-core kernel)
 };
 
 }  // namespace wide

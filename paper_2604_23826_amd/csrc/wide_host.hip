@@ -95,28 +95,17 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
   const size_t slot_bytes = up(sizeof(wide::SlotInfo) * (size_t)p);
   const int64_t nb_max = std::min<int64_t>(max_blocks, (nrows + R - 1) / R);
   const size_t ovf_bytes = up(sizeof(int) * (size_t)nb_max);
-  // record words the two halves of a diagonal pair both add into: every
-  // column sum and every product with an extra column
-  std::vector<int32_t> sumoffs;
-  for (int u = 0; u < p; ++u) sumoffs.push_back((int32_t)(2 + p + u));
-  for (int x = 0; x < ne; ++x) {
-    const int ue = col_of[F + x];
-    for (int u = 0; u < p; ++u) sumoffs.push_back((int32_t)(2 + 2 * p + tri(p, std::min(u, ue), std::max(u, ue))));
-  }
-  const size_t sumoff_bytes = up(sizeof(int32_t) * sumoffs.size());
-  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, col_bytes + tile_bytes + slot_bytes + ovf_bytes + sumoff_bytes);
+  const size_t sexp_bytes = up(sizeof(int) * (size_t)nb_max * (size_t)F);  // grid exponents
+  int rc = ensure_dev(h, &h->aux3_dev, &h->aux3_cap, col_bytes + tile_bytes + slot_bytes + ovf_bytes + sexp_bytes);
   if (rc) return rc;
   char* aux = (char*)h->aux3_dev;
   int32_t* col_dev = (int32_t*)aux;
   int2* tiles_dev = (int2*)(aux + col_bytes);
   wide::SlotInfo* slots_dev = (wide::SlotInfo*)(aux + col_bytes + tile_bytes);
   int* ovf_dev = (int*)(aux + col_bytes + tile_bytes + slot_bytes);
-  int32_t* sumoffs_dev = (int32_t*)(aux + col_bytes + tile_bytes + slot_bytes + ovf_bytes);
+  int* sexp_dev = (int*)(aux + col_bytes + tile_bytes + slot_bytes + ovf_bytes);
   hipError_t e = hipMemcpyAsync(col_dev, col_of.data(), sizeof(int32_t) * (size_t)p,
                                 hipMemcpyHostToDevice, h->stream);
-  if (e == hipSuccess)
-    e = hipMemcpyAsync(sumoffs_dev, sumoffs.data(), sizeof(int32_t) * sumoffs.size(), hipMemcpyHostToDevice,
-                       h->stream);
   if (e == hipSuccess)
     e = hipMemcpyAsync(tiles_dev, tiles.data(), sizeof(int2) * tiles.size(), hipMemcpyHostToDevice, h->stream);
   if (e != hipSuccess) return hip_fail(h, e, "uploading column map");
@@ -136,8 +125,7 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
   a.R = R;
   a.status = h->status_dev;
   a.ovf = ovf_dev;
-  a.sumoffs = sumoffs_dev;
-  a.nsumoffs = (int)sumoffs.size();
+  a.sexp = sexp_dev;
   std::vector<wide::SlotInfo> slots(p);
   int64_t done = 0;
   while (done < nrows) {

@@ -665,6 +665,8 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     m.s_exp[k] = s;
     m.s_sc[k] = valid ? ldexpf(1.0f, s) : 0.0f;
     m.s_nks[k] = valid ? -K * ldexpf(1.0f, s) : 0.0f;
+    // the grids of the block, for the sums pass (one writer per column)
+    if (DIAG && half == 0 && c.gcol(k) < a.F) a.sexp[b * a.F + c.gcol(k)] = s;
   }
   lds_barrier();
   if (m.s_flag[0]) {
@@ -896,6 +898,232 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   }
 }
 
+// ---- column sums, products with the extra columns, checks of the grids ----
+//
+// The rest of a block's record needs no matrix cores.  On the block's grids
+// every shifted value d = x - K has at most 22 significant bits, every
+// shifted integer extra at most the bits of the block's identifier range, and
+// the products and their sums over 32768 rows stay far below 2^53: formed in
+// FP64 from the FP32 values they are exact, so they equal the sums of the grid
+// integers scaled by 2^-s whatever the order.  d itself is formed in FP32,
+// exact on the grid.  The same pass checks every value against its grid: x 2^s
+// an integer (one v_fract), |d| 2^s <= 2^22 - 1, finite; a value that fails
+// flags the block for the FP64 routine (which also takes blocks already
+// flagged by the matrix-core kernel; they are skipped here).
+//
+// One workgroup per block and 256 vector columns.  Wave w takes rows
+// r0 + w + 4 k; its rows move from HBM to its own LDS ring by direct DMA
+// (one 1 KiB global_load_lds_dwordx4 per row, lane l bringing columns
+// 4 l .. 4 l + 3 of the chunk; lanes 0..15 bring the extras' words), four
+// rows a stage, three stages, two in flight, so the only wait is on the
+// wave's own vector-memory counter.  The waves' sums are added in a fixed
+// order at the end.  The first chunk also forms the extras' own sums and
+// products.
+constexpr int kSumThreads = 256;
+constexpr int kSumRPW = 4;                    // rows per wave and stage
+constexpr int kSumNS = 3;                     // stages per wave
+constexpr int kSumSB = kSumRPW * 1024 + 64;   // stage bytes: rows + extras' words
+
+__global__ __launch_bounds__(kSumThreads, 3) void k_syrk_sums(wide::SyrkArgs a) {
+  constexpr int NQ = NE * (NE + 1) / 2;
+  constexpr int NW4 = kSumThreads / 64;
+  constexpr int RED = 4 * 64 * (1 + NE) + NE + NQ;  // doubles per wave in the final sums
+  __shared__ __attribute__((aligned(16))) unsigned char s_ring[NW4 * kSumNS * kSumSB];
+  static_assert(sizeof(s_ring) >= NW4 * RED * sizeof(double), "the final sums reuse the ring");
+  const int F = a.F, p = a.p;
+  const int nch = (F + 255) / 256;
+  const int64_t b = blockIdx.x / nch;
+  const int cb = 256 * (int)(blockIdx.x % nch);  // first column of the chunk
+  if (a.ovf[b]) return;                          // recomputed in FP64
+  const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int ne = cb == 0 ? a.ne : 0;  // the extras' own sums: first chunk
+  const int ns = a.ne;                 // strips with the extras: every chunk
+  const int c0 = cb + 4 * lane;
+  const bool cv = c0 < F;  // F is a multiple of 4
+  float K[4], lim[4], sc[4];
+  {
+    const fl4 k4 = cv ? *(const fl4*)(a.xbase + r0 * a.xstride + 4 * (int64_t)c0) : (fl4){0.f, 0.f, 0.f, 0.f};
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      const int sx = cv ? a.sexp[b * F + c0 + i] : 0;
+      K[i] = k4[i];
+      sc[i] = ldexpf(1.0f, sx);
+      lim[i] = ldexpf(kVlim, -sx);  // exact: kVlim has 22 significant bits
+    }
+  }
+  double eK[NE];
+  int64_t eKi[NE];
+  bool e64[NE];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    eK[e] = 0.0;
+    eKi[e] = 0;
+    e64[e] = e < ns && wide_kind(a.ex[e].kind);
+    if (e < ns) extra_shift(a.ex[e], r0, eK[e], eKi[e]);
+  }
+  double S[4] = {0.0, 0.0, 0.0, 0.0}, ST[NE][4], es[NE], eq[NQ];
+#pragma unroll
+  for (int e = 0; e < NE; ++e) {
+    es[e] = 0.0;
+#pragma unroll
+    for (int i = 0; i < 4; ++i) ST[e][i] = 0.0;
+  }
+#pragma unroll
+  for (int q = 0; q < NQ; ++q) eq[q] = 0.0;
+  float fo = 0.0f;
+  bool over = false;
+  uint32_t bad = 0;
+
+  // rows of this wave: r0 + wave + 4 k, k < nk; stage t holds k = 4 t .. 4 t + 3
+  const int64_t nk = (r1 - r0 - wave + 3) / 4;
+  const int64_t nst = (nk + kSumRPW - 1) / kSumRPW;
+  unsigned char* ring = s_ring + wave * kSumNS * kSumSB;
+  const int64_t colb = cv ? c0 : cb;  // a valid column for idle lanes
+  const bool exl = lane < 16 && (lane >> 3) < ns && (((lane >> 2) & 1) == 0 || e64[lane >> 3]);
+  auto issue = [&](int64_t t) {
+    unsigned char* st = ring + (int)(t % kSumNS) * kSumSB;
+#pragma unroll
+    for (int j = 0; j < kSumRPW; ++j) {
+      int64_t r = r0 + wave + 4 * (kSumRPW * t + j);
+      r = r < r1 ? r : r1 - 1;
+      __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * colb),
+                                       (__attribute__((address_space(3))) void*)(st + j * 1024), 16, 0, 0);
+    }
+    if (ns > 0) {
+      // lane 8e + 4w + j: dword w of extra e in row j of the stage
+      if (exl) {
+        const int e = lane >> 3, wd = (lane >> 2) & 1, j = lane & 3;
+        int64_t r = r0 + wave + 4 * (kSumRPW * t + j);
+        r = r < r1 ? r : r1 - 1;
+        __builtin_amdgcn_global_load_lds((const void*)(a.ex[e].base + r * a.ex[e].stride + 4 * wd),
+                                         (__attribute__((address_space(3))) void*)(st + kSumRPW * 1024), 4, 0, 0);
+      }
+    }
+  };
+#pragma unroll
+  for (int t = 0; t < kSumNS - 1; ++t)
+    if (t < nst) issue(t);
+  for (int64_t t = 0; t < nst; ++t) {
+    // stage t is this wave's oldest outstanding group of loads
+    if (t + kSumNS - 2 < nst) {
+      if (ns > 0) __builtin_amdgcn_s_waitcnt(VmWait<(kSumNS - 2) * (kSumRPW + 1)>::imm);
+      else __builtin_amdgcn_s_waitcnt(VmWait<(kSumNS - 2) * kSumRPW>::imm);
+    } else {
+      __builtin_amdgcn_s_waitcnt(VmWait<0>::imm);
+    }
+    // the slot refilled next was read by this wave in the last iteration
+    if (t + kSumNS - 1 < nst) issue(t + kSumNS - 1);
+    const unsigned char* st = ring + (int)(t % kSumNS) * kSumSB;
+#pragma unroll
+    for (int j = 0; j < kSumRPW; ++j) {
+      if (kSumRPW * t + j >= nk) break;
+      const fl4 v = *(const __attribute__((address_space(3))) fl4*)(st + j * 1024 + 16 * lane);
+      double de[NE];
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        de[e] = 0.0;
+        if (e < ns) {
+          const __attribute__((address_space(3))) uint32_t* w =
+              (const __attribute__((address_space(3))) uint32_t*)(st + kSumRPW * 1024);
+          const uint32_t lo = w[8 * e + j], hi = w[8 * e + 4 + j];
+          const wide::SyrkExtra& x = a.ex[e];
+          switch (x.kind) {
+            case STATS_I32: de[e] = (double)(int32_t)lo - eK[e]; break;
+            case STATS_I64: de[e] = (double)((int64_t)(((uint64_t)hi << 32) | lo) - eKi[e]); break;
+            case STATS_F32: {
+              const double y = (double)__uint_as_float(lo);
+              if (x.chk) bad |= (y != __builtin_rint(y));
+              de[e] = y - eK[e];
+              break;
+            }
+            default: {
+              const double y = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
+              if (x.chk) bad |= (y != __builtin_rint(y));
+              de[e] = y - eK[e];
+            }
+          }
+        }
+      }
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        const float x = v[i];
+        const float d32 = x - K[i];  // exact on the grid
+        const double d = (double)d32;
+        S[i] += d;
+#pragma unroll
+        for (int e = 0; e < NE; ++e) ST[e][i] = __builtin_fma(d, de[e], ST[e][i]);
+        fo = fmaxf(fo, __builtin_amdgcn_fractf(x * sc[i]));
+        over |= !(fabsf(d32) <= lim[i]);
+      }
+      int q = 0;
+#pragma unroll
+      for (int e = 0; e < NE; ++e) {
+        es[e] += de[e];
+#pragma unroll
+        for (int g = e; g < NE; ++g, ++q) eq[q] = __builtin_fma(de[e], de[g], eq[q]);
+      }
+    }
+  }
+  over |= !(fo == 0.0f);
+  if (!cv) over = false;
+  if (over) a.ovf[b] = 1;
+  if (bad) atomicOr(&a.status->bits, ST_INEXACT);
+  __syncthreads();  // every wave is done with its ring
+  double* s_red = (double*)s_ring;
+  double* red = s_red + wave * RED;
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    red[4 * lane + i] = S[i];
+#pragma unroll
+    for (int e = 0; e < NE; ++e) red[256 * (1 + e) + 4 * lane + i] = ST[e][i];
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int e = 0; e < NE; ++e) red[256 * (1 + NE) + e] = es[e];
+#pragma unroll
+    for (int q = 0; q < NQ; ++q) red[256 * (1 + NE) + NE + q] = eq[q];
+  }
+  __syncthreads();
+  uint64_t* out = a.rec + b * rec_words(p);
+  for (int k = threadIdx.x; k < 256 && cb + k < F; k += kSumThreads) {
+    const int uc = a.col_of[cb + k];
+    double sum = s_red[k];
+#pragma unroll
+    for (int w = 1; w < NW4; ++w) sum += s_red[w * RED + k];
+    out[2 + p + uc] = (uint64_t)__double_as_longlong(sum);
+    out[2 + uc] = (uint64_t)__double_as_longlong((double)*(const float*)(a.xbase + r0 * a.xstride + 4 * (int64_t)(cb + k)));
+    for (int e = 0; e < ns; ++e) {
+      double st = s_red[256 * (1 + e) + k];
+#pragma unroll
+      for (int w = 1; w < NW4; ++w) st += s_red[w * RED + 256 * (1 + e) + k];
+      const int ue = a.col_of[F + e];
+      out[2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))] = (uint64_t)__double_as_longlong(st);
+    }
+  }
+  if (threadIdx.x == 0 && cb == 0) {
+    int q = 0;
+    for (int e = 0; e < NE; ++e) {
+      if (e < ne) {
+        double se = s_red[256 * (1 + NE) + e];
+        for (int w = 1; w < NW4; ++w) se += s_red[w * RED + 256 * (1 + NE) + e];
+        const int ue = a.col_of[F + e];
+        out[2 + p + ue] = (uint64_t)__double_as_longlong(se);
+        out[2 + ue] = shift_word(a.ex[e].isint, a.ex[e].kind, eK[e], eKi[e]);
+      }
+      for (int g = e; g < NE; ++g, ++q)
+        if (g < ne) {
+          double sq = s_red[256 * (1 + NE) + NE + q];
+          for (int w = 1; w < NW4; ++w) sq += s_red[w * RED + 256 * (1 + NE) + NE + q];
+          const int ue = a.col_of[F + e], uf = a.col_of[F + g];
+          out[2 + 2 * p + tri(p, min(ue, uf), max(ue, uf))] = (uint64_t)__double_as_longlong(sq);
+        }
+    }
+    out[0] = (uint64_t)(r1 - r0);
+    out[1] = 0;
+  }
+}
+
 __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   __shared__ __attribute__((aligned(16))) unsigned char s_ring[NST * STB];
   __shared__ __attribute__((aligned(16))) union {
@@ -927,7 +1155,7 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   m.s_ex = s_ex;
   m.s_flag = &s_flag;
   if (A != B) pair_block<false, false>(a, m, b, A, B, half);
-  else pair_block<true, true>(a, m, b, A, B, half);
+  else pair_block<true, false>(a, m, b, A, B, half);
 }
 
 __global__ void k_zero_flags(int* f, int64_t n) {
@@ -935,23 +1163,15 @@ __global__ void k_zero_flags(int* f, int64_t n) {
   if (i < n) f[i] = 0;
 }
 
-// Zeroes the record words the two halves of a diagonal pair add into: word
-// offs[k] of every record (grid: records x offsets).
-__global__ void k_zero_sum_slots(uint64_t* rec, int64_t W, const int* offs, int noffs, int64_t nrec) {
-  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < nrec * noffs) rec[(i / noffs) * W + offs[i % noffs]] = 0;
-}
-
 }  // namespace syrk
 
 void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s) {
   hipLaunchKernelGGL(syrk::k_zero_flags, dim3((unsigned)((a.nblocks + 255) / 256)), dim3(256), 0, s, a.ovf,
                      a.nblocks);
-  const int64_t nz = a.nblocks * a.nsumoffs;
-  hipLaunchKernelGGL(syrk::k_zero_sum_slots, dim3((unsigned)((nz + 255) / 256)), dim3(256), 0, s, a.rec,
-                     rec_words(a.p), a.sumoffs, a.nsumoffs, a.nblocks);
   const int64_t nb8 = (a.nblocks + 7) / 8 * 8;
   hipLaunchKernelGGL(syrk::k_syrk_i8, dim3((unsigned)(nb8 * a.npairs)), dim3(syrk::kThreads), 0, s, a);
+  const int64_t nch = (a.F + 255) / 256;
+  hipLaunchKernelGGL(syrk::k_syrk_sums, dim3((unsigned)(a.nblocks * nch)), dim3(syrk::kSumThreads), 0, s, a);
 }
 
 }  // namespace st
