@@ -29,29 +29,32 @@
 // few binades of the shift (and integers below 2^21) lie on it, so their
 // products are exact.
 //
-// A block with a value beyond its column's limit, a value off its grid
-// (x 2^s not an integer: one v_fract per value), or a non-finite value is
-// flagged (ovf[b]) by the diagonal pair that owns the column (every column
-// belongs to one); the FP64 matrix-core routine of wide.hip then computes
-// that block's whole record again (launch_wide_fixup), so every block is
-// either exact on its grid or FP64.  Each workgroup also finds the lowest set
-// bit of its first 128 sampled rows: when one lies below the grid spacing
-// the block cannot be exact (zero-mean data with full significands, say), and
-// the workgroup flags it and stops before the main loop.
+// Two passes per launch.  k_syrk_i8 forms the digits and the products above
+// and writes each block's grid exponents; k_syrk_sums then forms the rest of
+// the record (column sums, products with the extra columns, shifts, row
+// count) and checks every value: a block with a value beyond its column's
+// limit, a value off its grid (x 2^s not an integer: one v_fract per value),
+// or a non-finite value is flagged (ovf[b]), and the FP64 matrix-core routine
+// of wide.hip computes that block's whole record again (launch_wide_fixup),
+// so every block is either exact on its grid or FP64.  Each workgroup of the
+// first pass also finds the lowest set bit of its first 128 sampled rows:
+// when one lies below the grid spacing the block cannot be exact (zero-mean
+// data with full significands, say), and the workgroup flags it and stops
+// before the main loop.
 //
 // Work split: vector columns form groups of 128.  A workgroup owns one block
 // of rows and one half of a pair of groups (A, B), A <= B: two tile rows of
 // A for an off-diagonal pair (8 tiles), tile rows {0, 3} or {1, 2} of a
 // diagonal one (5 upper tiles).  Eight waves, two per SIMD, with one 32 x 32
 // tile each (its five int32 levels in 80 accumulation registers), so that
-// each wave's waits are covered by the other wave of its SIMD;
-// half 0 of a diagonal pair also sums its columns and forms their products
-// with the extra columns in FP64 on the vector units.  Workgroup ids put all
+// each wave's waits are covered by the other wave of its SIMD.  The sums stay
+// out of this pass: in the workgroups of the diagonal pairs they would double
+// the vector work on the pass's critical path.  Workgroup ids put all
 // pairs of one block on the same XCD (ids congruent modulo 8), so the block's
 // rows come from HBM once and from that XCD's L2 after.
 //
-// Data path per 32-row sub-step: each wave moves its own four rows (and
-// their extra-column values) from HBM into an LDS ring of three stages by
+// Data path per 32-row sub-step: each wave moves its own four rows from HBM
+// into an LDS ring of three stages by
 // direct DMA (global_load_lds, two sub-steps in flight) and converts exactly
 // those rows, so its only wait on the ring is its own vector-memory counter.
 // The digits go to a double-buffered LDS array, [digit][4-row group][column]
@@ -84,8 +87,7 @@ constexpr int G = wide::kSyrkGroup;  // vector columns per group
 constexpr int SR = 32;               // rows per sub-step (K of one product)
 constexpr int NST = 3;               // stages in the LDS ring
 constexpr int RAWB = SR * 2 * G * 4; // row bytes per stage (32 rows x 256 FP32)
-constexpr int EXW = 4 * RW;          // extra-column dwords per wave per stage
-constexpr int STB = RAWB + 8 * EXW * 4;  // stage bytes: rows, then the waves' extras
+constexpr int STB = RAWB;            // stage bytes
 constexpr int PITCH_MAX = 2 * G + 8;
 constexpr int NSAMP = 1024;          // rows sampled per block for the grids
 constexpr int SB = 16;               // sampled rows per wave in flight
@@ -93,7 +95,7 @@ constexpr float kVlim = 4194303.0f;  // |v| < 2^22: the rounding constant below 
 constexpr float kRound = 12582912.0f; // 1.5 * 2^23: y + kRound is rint(y) in the low mantissa bits
 constexpr int kBias = 0x8080 - 0x4B400000;  // bits(y + kRound) + kBias = v + 0x8080
 constexpr int NE = wide::kSyrkMaxExtra;
-static_assert(NE <= 2 && RW == 4, "extras: two columns of two dwords in four rows per wave");
+static_assert(NE <= 2, "the sums pass brings two dwords of at most two extras per row");
 
 // s_waitcnt immediate: at most N vector-memory loads of this wave outstanding.
 template <int N>
@@ -172,18 +174,6 @@ __device__ inline void raw_read2(uint32_t a, fl2 (&x)[4]) {
       : "v"(a));
 }
 
-// extras of four rows: x[2e] low dwords, x[2e + 1] high dwords of extra e
-__device__ inline void ex_read(uint32_t a, u4 (&x)[4]) {
-  asm volatile(
-      "ds_read_b128 %0, %4\n\t"
-      "ds_read_b128 %1, %4 offset:16\n\t"
-      "ds_read_b128 %2, %4 offset:32\n\t"
-      "ds_read_b128 %3, %4 offset:48\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
-      : "v"(a));
-}
-
 // Barrier after this wave's LDS writes, without waiting for the DMA loads in
 // flight (a __syncthreads() fence would wait for them too).
 __device__ inline void lds_barrier() { asm volatile("s_waitcnt lgkmcnt(0)\n\ts_barrier" ::: "memory"); }
@@ -226,19 +216,9 @@ __device__ inline int grid_exp(double m, float K) {
   return max(-126, min(127, s));
 }
 
-// One sub-step's per-lane sums, added into the running sums after the barrier.
-template <int CPL>
-struct Pending {
-  int is[CPL];         // sum of the lane's v per column (|sum| < 2^26)
-  double sp[NE][CPL];  // sum of v * (extra - K_e) per column
-  double es[NE];       // extras: sums and products of the wave's rows
-  double eq[NE * (NE + 1) / 2];
-};
-
-// DIAG: a diagonal half; SUMS: it also forms the column sums, the products
-// with the extra columns and the checks of the block (half 0 of a diagonal
-// pair: every column of the table is in exactly one such workgroup).
-template <bool DIAG, bool SUMS>
+// One workgroup's view of its block: DIAG for a half of a diagonal pair (one
+// group of columns), else a half of an off-diagonal pair (two groups).
+template <bool DIAG>
 struct Ctx {
   static constexpr int NC = Shape<DIAG>::NC;
   static constexpr int CPL = Shape<DIAG>::CPL;
@@ -249,21 +229,16 @@ struct Ctx {
   int* dig;             // LDS digits [2][3][8][PITCH]
   const float* s_sc;    // 2^s per staged column (0: not converted)
   const float* s_nks;   // -K 2^s
-  const double* s_eK;   // shifts of the extra columns
-  const int64_t* s_eKi;
   int64_t r0, r1;
-  int A, B, lane, wave, h, q, ne;
+  int A, B, lane, wave, h, q;
   int cl0;              // first staged column converted by this lane
-  bool over;            // a value left its grid or was not finite
-  uint32_t bad;
 
   __device__ Ctx(const wide::SyrkArgs& a_) : a(a_) {}
 
   // global vector column of staged column c
   __device__ __attribute__((always_inline)) int gcol(int c) const { return DIAG ? A * G + c : (c < G ? A * G + c : B * G + (c - G)); }
 
-  // DMA of this wave's rows of sub-step t (and their extra values) into
-  // stage t % NST: a fixed number of instructions, every lane active on the
+  // DMA of this wave's rows of sub-step t into stage t % NST: a fixed number of instructions, every lane active on the
   // row loads (rows past the block end read its last row, columns past F
   // read column 0; both are ignored).
   __device__ __attribute__((always_inline)) void issue(int64_t t) const {
@@ -280,17 +255,6 @@ struct Ctx {
         __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * col),
                                          (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
       }
-      if (ne > 0) {
-        // lane 8e + 4w + j: dword w of extra e in row j (lanes >= 16 idle)
-        const int e = lane >> 3, wd = (lane >> 2) & 1, j = lane & 3;
-        if (lane < 16 && e < ne && (wd == 0 || wide_kind(a.ex[e].kind))) {
-          int64_t r = rb + j;
-          r = r < r1 ? r : r1 - 1;
-          __builtin_amdgcn_global_load_lds((const void*)(a.ex[e].base + r * a.ex[e].stride + 4 * wd),
-                                           (__attribute__((address_space(3))) void*)(stage + RAWB + wave * EXW * 4),
-                                           4, 0, 0);
-        }
-      }
     } else {
       const int dc = gcol(4 * lane);
       const int64_t col = dc < a.F ? dc : 0;
@@ -305,9 +269,9 @@ struct Ctx {
   }
 
   // The same DMA for a sub-step that lies inside the block: the lane's row
-  // pointers are advanced by the caller (rp: this wave's first row of the
-  // sub-step, at the lane's column; ep: the lane's extra element), no clamps.
-  __device__ __attribute__((always_inline)) void issue_inside(int stage_i, const char* rp, const char* ep) const {
+  // pointer is advanced by the caller (rp: this wave's first row of the
+  // sub-step, at the lane's column), no clamps.
+  __device__ __attribute__((always_inline)) void issue_inside(int stage_i, const char* rp) const {
     unsigned char* stage = ring + stage_i * STB;
     unsigned char* dst = stage + RW * wave * RB;
     if constexpr (DIAG) {
@@ -315,13 +279,6 @@ struct Ctx {
       for (int m = 0; m < RW / 2; ++m)
         __builtin_amdgcn_global_load_lds((const void*)(rp + 2 * m * a.xstride),
                                          (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
-      if (ne > 0) {
-        const int e = lane >> 3, wd = (lane >> 2) & 1;
-        if (lane < 16 && e < ne && (wd == 0 || wide_kind(a.ex[e].kind)))
-          __builtin_amdgcn_global_load_lds((const void*)ep,
-                                           (__attribute__((address_space(3))) void*)(stage + RAWB + wave * EXW * 4),
-                                           4, 0, 0);
-      }
     } else {
 #pragma unroll
       for (int j = 0; j < RW; ++j)
@@ -334,9 +291,7 @@ struct Ctx {
   // LATER (0, 1, 2) sub-steps issued after it
   template <int LATER>
   __device__ __attribute__((always_inline)) void wait_dma() const {
-    constexpr int n = Shape<DIAG>::NROW;
-    if (DIAG && ne > 0) __builtin_amdgcn_s_waitcnt(VmWait<LATER * (n + 1)>::imm);
-    else __builtin_amdgcn_s_waitcnt(VmWait<LATER * n>::imm);
+    __builtin_amdgcn_s_waitcnt(VmWait<LATER * Shape<DIAG>::NROW>::imm);
   }
 
   __device__ __attribute__((always_inline)) uint32_t lds(const void* p) const { return (uint32_t)(uintptr_t)p; }
@@ -370,71 +325,20 @@ struct Ctx {
     }
   }
 
-  // extra e's shifted value in row j (0..3) of a group of fetched dwords
-  __device__ __attribute__((always_inline)) double extra_of(const u4 (&w)[4], int e, int j) {
-    const uint32_t lo = w[2 * e][j], hi = w[2 * e + 1][j];
-    const wide::SyrkExtra& x = a.ex[e];
-    switch (x.kind) {
-      case STATS_I32: return (double)(int32_t)lo - s_eK[e];
-      case STATS_I64: return (double)((int64_t)(((uint64_t)hi << 32) | lo) - s_eKi[e]);
-      case STATS_F32: {
-        const double y = (double)__uint_as_float(lo);
-        if (x.chk) bad |= (y != __builtin_rint(y));
-        return y - s_eK[e];
-      }
-      default: {
-        const double y = __longlong_as_double((long long)(((uint64_t)hi << 32) | lo));
-        if (x.chk) bad |= (y != __builtin_rint(y));
-        return y - s_eK[e];
-      }
-    }
-  }
-
-  // Digits of sub-step t into digit buffer t & 1; with DOSUMS (in a SUMS
-  // workgroup, on the sub-steps of its parity) also the sums of v, its
-  // products with the extras and the checks of grid, limit and finiteness.
-  template <bool TAIL, bool DOSUMS>
-  __device__ __attribute__((always_inline)) void digitize(int64_t t, int stage_i, Raw& r, Pending<CPL>& pd) {
-    constexpr bool DS = SUMS && DOSUMS;
-    float sc[CPL], nks[CPL], mx[CPL], fs[CPL], fo[CPL];
-    int sw[CPL];
+  // Digits of sub-step t into digit buffer t & 1 (rows past the block end
+  // give zeros).
+  template <bool TAIL>
+  __device__ __attribute__((always_inline)) void digitize(int64_t t, Raw& r) {
+    float sc[CPL], nks[CPL];
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       sc[i] = s_sc[cl0 + i];
       nks[i] = s_nks[cl0 + i];
-      mx[i] = fs[i] = fo[i] = 0.0f;
-      sw[i] = 0;
-#pragma unroll
-      for (int e = 0; e < NE; ++e) pd.sp[e][i] = 0.0;
     }
-#pragma unroll
-    for (int e = 0; e < NE; ++e) pd.es[e] = 0.0;
-#pragma unroll
-    for (int k = 0; k < NE * (NE + 1) / 2; ++k) pd.eq[k] = 0.0;
     const int64_t rb = r0 + t * SR + RW * wave;
 #pragma unroll
     for (int g = 0; g < RW / 4; ++g) {
       uint32_t dw[3][CPL];
-      double de[4][NE];
-      if (DS && ne > 0) {
-        u4 ew[4];
-        ex_read(lds(ring) + (uint32_t)(stage_i * STB + RAWB + wave * EXW * 4 + 16 * g), ew);
-#pragma unroll
-        for (int jj = 0; jj < 4; ++jj) {
-          const bool live = !TAIL || rb + 4 * g + jj < r1;
-#pragma unroll
-          for (int e = 0; e < NE; ++e) de[jj][e] = (e < ne && live) ? extra_of(ew, e, jj) : 0.0;
-          if (A == 0 && lane == 0) {
-            int tq = 0;
-#pragma unroll
-            for (int e = 0; e < NE; ++e) {
-              pd.es[e] += de[jj][e];
-#pragma unroll
-              for (int f = e; f < NE; ++f, ++tq) pd.eq[tq] = __builtin_fma(de[jj][e], de[jj][f], pd.eq[tq]);
-            }
-          }
-        }
-      }
 #pragma unroll
       for (int i = 0; i < CPL; ++i) {
         int w[4];
@@ -444,22 +348,6 @@ struct Ctx {
           if (TAIL) y = (rb + 4 * g + jj < r1) ? y : 0.0f;
           const float fr = y + kRound;
           w[jj] = __float_as_int(fr) + kBias;  // v + 0x8080: bytes d2 + 128, d1 + 128, d0
-          if constexpr (DS) {
-            // on the grid: x 2^s is an integer (K is too: it is the first
-            // row); the fraction is exact, so this test is too
-            float xf = __builtin_amdgcn_fractf(r.x[4 * g + jj][i] * sc[i]);
-            if (TAIL) xf = (rb + 4 * g + jj < r1) ? xf : 0.0f;
-            fo[i] = fmaxf(fo[i], xf);
-            mx[i] = fmaxf(mx[i], fabsf(y));
-            fs[i] += y;  // NaN and infinity show here
-            sw[i] += w[jj];
-            if (ne > 0) {
-              const double v = (double)(fr - kRound);
-#pragma unroll
-              for (int e = 0; e < NE; ++e)
-                if (e < ne) pd.sp[e][i] = __builtin_fma(v, de[jj][e], pd.sp[e][i]);
-            }
-          }
         }
         // byte transpose: digit k of the four rows into one dword
         const uint32_t p01 = __builtin_amdgcn_perm(w[1], w[0], 0x05010400u);
@@ -475,13 +363,6 @@ struct Ctx {
       for (int d = 0; d < 3; ++d) {
         if constexpr (CPL == 4) *(u4*)(out + d * 8 * PITCH) = (u4){dw[d][0], dw[d][1], dw[d][2], dw[d][3]};
         else *(u2*)(out + d * 8 * PITCH) = (u2){dw[d][0], dw[d][1]};
-      }
-    }
-    if constexpr (DS) {
-#pragma unroll
-      for (int i = 0; i < CPL; ++i) {
-        over |= !(mx[i] <= kVlim) | !(fabsf(fs[i]) <= 3.0e38f) | !(fo[i] == 0.0f);
-        pd.is[i] = sw[i] - RW * 0x8080;
       }
     }
   }
@@ -533,25 +414,20 @@ struct Lds {
   float* s_K;
   float* s_sc;
   float* s_nks;
-  double* s_eK;
-  int64_t* s_eKi;
-  double* s_ex;     // [NW][8]: extras' per-wave sums and products
   int* s_flag;      // sampled values off their grid: the block goes to FP64
 };
 
 // One block of rows and one pair of column groups (A, B).
-template <bool DIAG, bool SUMS>
+template <bool DIAG>
 __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& a, const Lds& m, int64_t b, int A,
                                                          int B, int half) {
   constexpr int NC = Shape<DIAG>::NC;
   constexpr int CPL = Shape<DIAG>::CPL;
-  Ctx<DIAG, SUMS> c(a);
+  Ctx<DIAG> c(a);
   c.ring = m.ring;
   c.dig = m.dig;
   c.s_sc = m.s_sc;
   c.s_nks = m.s_nks;
-  c.s_eK = m.s_eK;
-  c.s_eKi = m.s_eKi;
   c.r0 = b * a.R;
   c.r1 = min(c.r0 + a.R, a.nrows);
   c.A = A;
@@ -560,16 +436,12 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   c.wave = __builtin_amdgcn_readfirstlane(threadIdx.x >> 6);
   c.h = c.lane >> 5;
   c.q = c.lane & 31;
-  c.ne = SUMS ? a.ne : 0;
   c.cl0 = CPL * c.lane;
-  c.over = false;
-  c.bad = 0;
   const bool colv = c.gcol(c.cl0) < a.F;
   const int64_t nrow = c.r1 - c.r0;
   const int64_t nsub = (nrow + SR - 1) / SR;
   const int tid = threadIdx.x;
   uint64_t* out = a.rec + b * rec_words(a.p);
-  const bool self = SUMS && A == 0 && c.ne > 0 && c.lane == 0;
 
   c.issue(0);
   if (nsub > 1) c.issue(1);
@@ -581,21 +453,10 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     m.s_exp[k] = 0x7FFFFFFF;  // lowest set bit of the sampled values, below
   }
   if (tid == 0) m.s_flag[0] = 0;
-  if (SUMS && tid < c.ne) {
-    double K;
-    int64_t Ki;
-    extra_shift(a.ex[tid], c.r0, K, Ki);
-    m.s_eK[tid] = K;
-    m.s_eKi[tid] = Ki;
-  }
-  if (self) {
-    for (int k = 0; k < 8; ++k) m.s_ex[c.wave * 8 + k] = 0.0;
-  }
   lds_barrier();
   {
     double K[CPL], mx[CPL];
     int lb[CPL];
-    bool fin = true;
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       K[i] = (double)m.s_K[c.cl0 + i];
@@ -625,10 +486,7 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
 #pragma unroll
       for (int u = 0; u < SB; ++u)
 #pragma unroll
-        for (int i = 0; i < CPL; ++i) {
-          fin &= __builtin_isfinite(x[u][i]);
-          mx[i] = fmax(mx[i], fabs((double)x[u][i] - K[i]));
-        }
+        for (int i = 0; i < CPL; ++i) mx[i] = fmax(mx[i], fabs((double)x[u][i] - K[i]));
       if (k0 == c.wave) {
         // the first NW x SB samples: exponent of each value's lowest set
         // bit (x = sig 2^(E - 150) for a normal FP32 value)
@@ -644,7 +502,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
           }
       }
     }
-    if (SUMS && !fin && colv) c.over = true;
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       m.red[c.wave * NC + c.cl0 + i] = mx[i];
@@ -676,42 +533,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     return;
   }
 
-  // running sums of the diagonal pair: column sums, strips with the extras
-  double S[CPL], strip[NE][CPL];
-#pragma unroll
-  for (int i = 0; i < CPL; ++i) {
-    S[i] = 0.0;
-#pragma unroll
-    for (int e = 0; e < NE; ++e) strip[e][i] = 0.0;
-  }
-  Pending<CPL> pd;
-  // the sums of sub-step t belong to the half of its parity (both halves of
-  // a diagonal pair are SUMS workgroups; each takes every other sub-step)
-  auto sums_at = [&](int64_t t) { return SUMS && (int)(t & 1) == half; };
-  auto commit = [&](bool now) {
-    if (!now) return;
-    if constexpr (SUMS) {
-#pragma unroll
-      for (int i = 0; i < CPL; ++i) {
-        const double pw = ldexp(1.0, -m.s_exp[c.cl0 + i]);
-        S[i] = __builtin_fma((double)pd.is[i], pw, S[i]);
-#pragma unroll
-        for (int e = 0; e < NE; ++e)
-          if (e < c.ne) strip[e][i] = __builtin_fma(pd.sp[e][i], pw, strip[e][i]);
-      }
-    }
-    if (self) {
-      double* x = m.s_ex + c.wave * 8;
-      int tq = 0;
-#pragma unroll
-      for (int e = 0; e < NE; ++e) {
-        if (e < c.ne) x[e] += pd.es[e];
-#pragma unroll
-        for (int f = e; f < NE; ++f, ++tq)
-          if (f < c.ne) x[NE + tq] += pd.eq[tq];
-      }
-    }
-  };
   const WaveTiles wt = wave_tiles<DIAG>(c.wave, half);
   // tiles that hold vector columns: a prefix of the wave's list
   int nt = 0;
@@ -727,20 +548,14 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
 #pragma unroll
     for (int l = 0; l < 5; ++l) L[u][l] = (i16){};
 
-  typename Ctx<DIAG, SUMS>::Raw raw;
+  typename Ctx<DIAG>::Raw raw;
   if (nsub > 2) c.template wait_dma<2>();
   else if (nsub > 1) c.template wait_dma<1>();
   else c.template wait_dma<0>();
   c.fetch(0, raw);
-  auto digits = [&](int64_t tt, int st, auto tail_c) __attribute__((always_inline)) {
-    constexpr bool TL = decltype(tail_c)::value;
-    if (sums_at(tt)) c.template digitize<TL, true>(tt, st, raw, pd);
-    else c.template digitize<TL, false>(tt, st, raw, pd);
-  };
-  if (SR > nrow) digits(0, 0, std::true_type{});
-  else digits(0, 0, std::false_type{});
+  if (SR > nrow) c.template digitize<true>(0, raw);
+  else c.template digitize<false>(0, raw);
   lds_barrier();
-  commit(sums_at(0));
   // Sub-step t: DMA of t + 3 into the stage of t (fetched into registers
   // one sub-step ago), fetch of t + 1 (its DMA was issued two sub-steps
   // ago), products of t, digits of t + 1 (the vector work can fill the
@@ -749,20 +564,11 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   // row pointers of sub-step t + 3 for the DMA inside the block
   const int64_t step_bytes = (int64_t)SR * a.xstride;
   const char* rp;
-  const char* ep = nullptr;
-  int64_t ep_step = 0;
   {
     const int dc = DIAG ? A * G + 4 * (c.lane & 31) : c.gcol(4 * c.lane);
     const int64_t col = dc < a.F ? dc : 0;
     const int64_t r = c.r0 + 3 * SR + RW * c.wave + (DIAG ? c.h : 0);
     rp = a.xbase + r * a.xstride + 4 * col;
-    if (SUMS && c.ne > 0) {
-      const int e = c.lane >> 3, wd = (c.lane >> 2) & 1, j = c.lane & 3;
-      if (c.lane < 16 && e < c.ne) {
-        ep = a.ex[e].base + (c.r0 + 3 * SR + RW * c.wave + j) * a.ex[e].stride + 4 * wd;
-        ep_step = (int64_t)SR * a.ex[e].stride;
-      }
-    }
   }
   auto step = [&](int64_t t, int s_t, auto more_c, auto issue_c, auto later_c, auto tail_c) __attribute__((always_inline)) {
     constexpr bool MORE = decltype(more_c)::value;
@@ -770,16 +576,15 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     constexpr int LATER = decltype(later_c)::value;
     constexpr bool TAIL = decltype(tail_c)::value;
     const int s_next = s_t == NST - 1 ? 0 : s_t + 1;  // stage of t + 1
-    if constexpr (ISSUE == 1) c.issue_inside(s_t, rp, ep);  // t + 3 lands in the stage of t
+    if constexpr (ISSUE == 1) c.issue_inside(s_t, rp);  // t + 3 lands in the stage of t
     if constexpr (ISSUE == 2) c.issue(t + 3);
     if constexpr (MORE) {
       c.template wait_dma<LATER>();
       c.fetch(s_next, raw);
     }
     mma_step<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, L);
-    if constexpr (MORE) digits(t + 1, s_next, tail_c);
+    if constexpr (MORE) c.template digitize<TAIL>(t + 1, raw);
     lds_barrier();
-    if constexpr (MORE) commit(sums_at(t + 1));
   };
   using T_ = std::true_type;
   using F_ = std::false_type;
@@ -792,7 +597,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; ++t) {
     step(t, s_t, T_{}, I1{}, I2{}, F_{});
     rp += step_bytes;
-    ep += ep_step;
     s_t = s_t == NST - 1 ? 0 : s_t + 1;
   }
   for (; t + 3 < nsub; ++t) {
@@ -811,8 +615,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     s_t = s_t == NST - 1 ? 0 : s_t + 1;
   }
   step(t, s_t, F_{}, I0{}, I0{}, F_{});
-  if (c.over) a.ovf[b] = 1;  // this block is computed again in FP64
-  if (c.bad) atomicOr(&a.status->bits, ST_INEXACT);
 
   // ---- tiles: levels combined, scaled by the grids, into the record ----
   const int p = a.p;
@@ -836,63 +638,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
         const int ua = a.col_of[ca];
         out[2 + 2 * p + tri(p, min(ua, ub), max(ua, ub))] =
             (uint64_t)__double_as_longlong(ldexp(P, 32 - m.s_exp[sal] - sb));
-      }
-    }
-  }
-  if (!SUMS) return;
-
-  // ---- column sums, K, strips: fixed-order sums over the waves ----
-  auto reduce_write = [&](const double (&v)[CPL], int extra) {
-    lds_barrier();
-#pragma unroll
-    for (int i = 0; i < CPL; ++i) m.red[c.wave * NC + c.cl0 + i] = v[i];
-    lds_barrier();
-    for (int k = tid; k < NC; k += kThreads) {
-      const int cg = A * G + k;
-      double sum = m.red[k];
-#pragma unroll
-      for (int w = 1; w < NW; ++w) sum += m.red[w * NC + k];
-      if (cg < a.F) {
-        const int uc = a.col_of[cg];
-        // the two halves' partial sums meet in slots zeroed before the
-        // launch; each part and their sum are exact, so the order of the
-        // two additions does not matter
-        if (extra < 0) {
-          atomicAdd((double*)(out + 2 + p + uc), sum);
-          out[2 + uc] = (uint64_t)__double_as_longlong((double)m.s_K[k]);
-        } else {
-          const int ue = a.col_of[a.F + extra];
-          atomicAdd((double*)(out + 2 + 2 * p + tri(p, min(uc, ue), max(uc, ue))), sum);
-        }
-      }
-    }
-  };
-  reduce_write(S, -1);
-#pragma unroll
-  for (int e = 0; e < NE; ++e)
-    if (e < c.ne) reduce_write(strip[e], e);
-  if (A == 0) {
-    lds_barrier();
-    if (tid == 0) {
-      int tq = 0;
-      for (int e = 0; e < c.ne; ++e) {
-        double s = m.s_ex[e];
-        for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + e];
-        const int ue = a.col_of[a.F + e];
-        atomicAdd((double*)(out + 2 + p + ue), s);
-        out[2 + ue] = shift_word(a.ex[e].isint, a.ex[e].kind, m.s_eK[e], m.s_eKi[e]);
-      }
-      for (int e = 0; e < NE; ++e)
-        for (int f = e; f < NE; ++f, ++tq)
-          if (f < c.ne) {
-            double s = m.s_ex[NE + tq];
-            for (int w = 1; w < NW; ++w) s += m.s_ex[w * 8 + NE + tq];
-            const int ue = a.col_of[a.F + e], uf = a.col_of[a.F + f];
-            atomicAdd((double*)(out + 2 + 2 * p + tri(p, min(ue, uf), max(ue, uf))), s);
-          }
-      if (half == 0) {
-        out[0] = (uint64_t)nrow;
-        out[1] = 0;
       }
     }
   }
@@ -1132,9 +877,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   } s_u;
   __shared__ int s_exp[2 * G];
   __shared__ float s_K[2 * G], s_sc[2 * G], s_nks[2 * G];
-  __shared__ double s_eK[NE];
-  __shared__ int64_t s_eKi[NE];
-  __shared__ double s_ex[NW * 8];
   __shared__ int s_flag;
   const int64_t id = blockIdx.x;
   const int64_t xcd = id & 7, y = id >> 3;
@@ -1150,12 +892,9 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   m.s_K = s_K;
   m.s_sc = s_sc;
   m.s_nks = s_nks;
-  m.s_eK = s_eK;
-  m.s_eKi = s_eKi;
-  m.s_ex = s_ex;
   m.s_flag = &s_flag;
-  if (A != B) pair_block<false, false>(a, m, b, A, B, half);
-  else pair_block<true, false>(a, m, b, A, B, half);
+  if (A != B) pair_block<false>(a, m, b, A, B, half);
+  else pair_block<true>(a, m, b, A, B, half);
 }
 
 __global__ void k_zero_flags(int* f, int64_t n) {
