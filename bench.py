@@ -465,7 +465,8 @@ def run_wide(args, L, torch, datagen):
                     {"workload": f"gauss_fp32_{N}x256_plus_int32_id", "rows": N, "p": p,
                      "bytes_per_row": bytes_row,
                      "step": "reset + accumulate (int8 digit products on the matrix cores) + sync"})
-    out["roofline"] = hbm_roofline("k_syrk_i8 (int8 digits on the matrix cores)", N * bytes_row,
+    out["roofline"] = hbm_roofline("k_syrk_i8 + k_syrk_sums (int8 digit products on the matrix cores, "
+                                   "then the sums and grid checks)", N * bytes_row,
                                    sp["syrk_ms"], int(round(launches)), N * bytes_row / launches,
                                    traffic_from_profile(N / launches, "wide"))
     algo = 2.0 * N * T / (sp["syrk_ms"] / 1e3) / 1e12
