@@ -16,10 +16,11 @@ matrix-core rate) against its peak, timed with HIP events on the library's
 stream, and the CPU oracle timed on a bounded sample of the same rows.
 
 Other workloads (--workload): c1 (10^6 FP64 Table-1 rows, --rows to sweep),
-wide (10^8 x 256 FP32 Gaussian columns + identifier, split-BF16 and FP64
-matrix-core modes), groups (4096 log-uniform groups of 32 columns, in waves),
-text (10^8 CSV lines in 1 GiB chunks), share --host-staged (the same share
-streamed from pinned host memory).
+wide (10^8 x 256 FP32 Gaussian columns + identifier, int8-digit split and
+FP64 matrix-core modes), groups (4096 log-uniform groups of 32 columns, in
+waves), text (10^8 CSV lines in 1 GiB chunks), share --host-pageable (the
+same share streamed from pageable host memory through the pinned ring) and
+share --host-staged (from pinned host memory, as much as can be page-locked).
 """
 import argparse
 import hashlib
