@@ -304,3 +304,35 @@ def test_auto_precision_picks_int8_kernel_or_fp64():
     ref = float(st.C_exact[oracle.tri_index(p, 8, 8)])
     for k in ("auto", "soa_auto"):
         assert abs(res[k]["C_f64"][8, 8] - ref) <= 1e-12 * ref, k
+
+
+@pytest.mark.parametrize("F", [260, 384])
+def test_split_more_than_256_vector_columns(F):
+    """Tables wider than one 256-column chunk of the sums pass (and than two
+    128-column groups of the matrix-core pass): an identifier plus F FP32
+    columns, a ragged last block.  Split against FP64 mode on every entry,
+    both against the oracle on the finalized outputs."""
+    print(f"split F={F}", flush=True)
+    L = lib()
+    p, n = F + 1, 9_001
+    x = gauss.rows_host(19, n, F)
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    planes = [to_dev(x), to_dev(ident)]
+    res = {}
+    for name, prec in (("fp64", L.STATS_PREC_FP64), ("split", L.STATS_PREC_SPLIT)):
+        res[name] = _run(L, _c3_config(L, p, precision=prec, block_rows=4096), planes, n, p)
+    C64, Csp = res["fp64"][0]["C_f64"], res["split"][0]["C_f64"]
+    d = np.sqrt(np.abs(np.diag(C64)))
+    scale = np.outer(d, d)
+    scale[scale == 0] = 1.0
+    assert np.max(np.abs(Csp - C64)[1:, 1:] / scale[1:, 1:]) <= 1e-13
+    assert res["split"][0]["s_int"][0] == n * (n + 1) // 2
+    st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(F)], [True] + [False] * F, threads=8)
+    ref = oracle.finalize(st, mask=range(1, p))
+    for name in ("fp64", "split"):
+        fin = res[name][1]
+        assert corr_scaled_err(fin["cov"], ref["cov"]) <= 1e-12, name
+        # means of 1e3..1e5: a few ulps of the mean, as for the narrow path
+        tol_mean = 1e-13 * np.abs(ref["mean"]) + 1e-12 * np.sqrt(np.diag(ref["cov"]))
+        assert np.all(np.abs(fin["mean"] - ref["mean"]) <= tol_mean), name
+        assert np.max(np.abs(fin["eigval"] - ref["eigval"])) <= 1e-12 * np.max(ref["eigval"]), name
