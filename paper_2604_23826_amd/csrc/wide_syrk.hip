@@ -130,8 +130,8 @@ __device__ inline WaveTiles wave_tiles(int w, int half) {
     return r;
   }
   // a diagonal half: the upper tiles of tile rows {0, 3} (half 0) or {1, 2}
-  // (half 1) of the 4 x 4 tiles, one per wave; waves without a tile run the
-  // same product code on a dummy one
+  // (half 1) of the 4 x 4 tiles, one per wave; waves without a tile only
+  // stage and convert rows
   switch (half * 8 + w) {
     case 0: r.n = 1; r.ti[0] = 0; r.tj[0] = 0; break;
     case 1: r.n = 1; r.ti[0] = 0; r.tj[0] = 1; break;
@@ -229,6 +229,7 @@ struct Ctx {
   int* dig;             // LDS digits [2][3][8][PITCH]
   const float* s_sc;    // 2^s per staged column (0: not converted)
   const float* s_nks;   // -K 2^s
+  float sc[CPL], nks[CPL];  // the lane's columns' 2^s and -K 2^s, in registers for the block
   int64_t r0, r1;
   int A, B, lane, wave, h, q;
   int cl0;              // first staged column converted by this lane
@@ -327,14 +328,16 @@ struct Ctx {
 
   // Digits of sub-step t into digit buffer t & 1 (rows past the block end
   // give zeros).
-  template <bool TAIL>
-  __device__ __attribute__((always_inline)) void digitize(int64_t t, Raw& r) {
-    float sc[CPL], nks[CPL];
+  __device__ __attribute__((always_inline)) void load_grids() {
 #pragma unroll
     for (int i = 0; i < CPL; ++i) {
       sc[i] = s_sc[cl0 + i];
       nks[i] = s_nks[cl0 + i];
     }
+  }
+
+  template <bool TAIL>
+  __device__ __attribute__((always_inline)) void digitize(int64_t t, Raw& r) const {
     const int64_t rb = r0 + t * SR + RW * wave;
 #pragma unroll
     for (int g = 0; g < RW / 4; ++g) {
@@ -378,32 +381,32 @@ __device__ inline i4 operand(const int* base, int d, int c) {
   return r;
 }
 
-// Products of one sub-step's digits (buffer buf) into the wave's tiles
-// (2 on an off-diagonal half, 3 on a diagonal pair; tiles past the last
-// vector column multiply zero digits and are not written): digit d of the
-// B operand meets the three digits of A in levels d..d+2; consecutive
-// products go to different tiles.
+// Operands of one sub-step's digits (buffer buf) for the wave's tile: the
+// three digits of its column block of A and of its column block of B.
+struct Ops {
+  i4 fa[3], fb[3];
+};
+
 template <bool DIAG>
-__device__ inline void mma_step(const int* dig, int buf, const WaveTiles& wt, int h, int q, i16 (&L)[MT][5]) {
+__device__ inline void load_ops(const int* dig, int buf, const WaveTiles& wt, int h, int q, Ops& o) {
   constexpr int PITCH = Shape<DIAG>::PITCH;
-  constexpr int NT = MT;
   const int* base = dig + (buf * 3 * 8 + 4 * h) * PITCH + q;
   constexpr int boff = DIAG ? 0 : G;
-  // all of a wave's tiles are in one tile row: one A operand
-  i4 fa[3];
-#pragma unroll
-  for (int d = 0; d < 3; ++d) fa[d] = operand<DIAG>(base, d, 32 * wt.ti[0]);
 #pragma unroll
   for (int d = 0; d < 3; ++d) {
-    i4 fb[NT];
-#pragma unroll
-    for (int u = 0; u < NT; ++u) fb[u] = operand<DIAG>(base, d, boff + 32 * wt.tj[u]);
-#pragma unroll
-    for (int k = 0; k < 3; ++k)
-#pragma unroll
-      for (int u = 0; u < NT; ++u)
-        L[u][d + k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(fa[k], fb[u], L[u][d + k], 0, 0, 0);
+    o.fa[d] = operand<DIAG>(base, d, 32 * wt.ti[0]);
+    o.fb[d] = operand<DIAG>(base, d, boff + 32 * wt.tj[0]);
   }
+}
+
+// The nine digit products of one sub-step into the tile's levels: digit d of
+// the B operand meets the three digits of A in levels d..d+2 (tiles past the
+// last vector column multiply zero digits and are not written).
+__device__ inline void mma_ops(const Ops& o, i16 (&L)[MT][5]) {
+#pragma unroll
+  for (int d = 0; d < 3; ++d)
+#pragma unroll
+    for (int k = 0; k < 3; ++k) L[0][d + k] = __builtin_amdgcn_mfma_i32_32x32x32_i8(o.fa[k], o.fb[d], L[0][d + k], 0, 0, 0);
 }
 
 struct Lds {
@@ -533,14 +536,14 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
     return;
   }
 
+  c.load_grids();
   const WaveTiles wt = wave_tiles<DIAG>(c.wave, half);
-  // tiles that hold vector columns: a prefix of the wave's list
+  // whether the wave has a tile that holds vector columns (a short last
+  // group leaves some tiles out); 0: no products
   int nt = 0;
 #pragma unroll
   for (int u = 0; u < MT; ++u)
     if (u < wt.n && A * G + 32 * wt.ti[u] < a.F && B * G + 32 * wt.tj[u] < a.F) nt = u + 1;
-  // (a diagonal pair's lists put the tiles a short last group leaves out last,
-  // except wave 3's transposed (3, 0), which is valid whenever (3, 3) is)
   nt = __builtin_amdgcn_readfirstlane(nt);
   i16 L[MT][5];
 #pragma unroll
@@ -557,64 +560,81 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   else c.template digitize<false>(0, raw);
   lds_barrier();
   // Sub-step t: DMA of t + 3 into the stage of t (fetched into registers
-  // one sub-step ago), fetch of t + 1 (its DMA was issued two sub-steps
-  // ago), products of t, digits of t + 1 (the vector work can fill the
-  // matrix-core shadow).  Branch-free in the main loop; the last three
-  // sub-steps are peeled.
+  // one sub-step ago), operands of t, fetch of t + 1 (its DMA was issued two
+  // sub-steps ago), products of t and digits of t + 1, interleaved so that
+  // the conversion's vector instructions issue while the matrix cores work.
+  // Branch-free in the main loop; the last three sub-steps are peeled.  Waves
+  // without a tile run the same loop without the products (same barriers).
   // row pointers of sub-step t + 3 for the DMA inside the block
   const int64_t step_bytes = (int64_t)SR * a.xstride;
-  const char* rp;
+  const char* rp0;
   {
     const int dc = DIAG ? A * G + 4 * (c.lane & 31) : c.gcol(4 * c.lane);
     const int64_t col = dc < a.F ? dc : 0;
     const int64_t r = c.r0 + 3 * SR + RW * c.wave + (DIAG ? c.h : 0);
-    rp = a.xbase + r * a.xstride + 4 * col;
+    rp0 = a.xbase + r * a.xstride + 4 * col;
   }
-  auto step = [&](int64_t t, int s_t, auto more_c, auto issue_c, auto later_c, auto tail_c) __attribute__((always_inline)) {
-    constexpr bool MORE = decltype(more_c)::value;
-    constexpr int ISSUE = decltype(issue_c)::value;  // 0: none, 1: inside the block, 2: clamped
-    constexpr int LATER = decltype(later_c)::value;
-    constexpr bool TAIL = decltype(tail_c)::value;
-    const int s_next = s_t == NST - 1 ? 0 : s_t + 1;  // stage of t + 1
-    if constexpr (ISSUE == 1) c.issue_inside(s_t, rp);  // t + 3 lands in the stage of t
-    if constexpr (ISSUE == 2) c.issue(t + 3);
-    if constexpr (MORE) {
-      c.template wait_dma<LATER>();
-      c.fetch(s_next, raw);
-    }
-    mma_step<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, L);
-    if constexpr (MORE) c.template digitize<TAIL>(t + 1, raw);
-    lds_barrier();
-  };
   using T_ = std::true_type;
   using F_ = std::false_type;
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
   using I2 = std::integral_constant<int, 2>;
-  int64_t t = 0;
-  int s_t = 0;  // t % NST
-  // sub-steps t + 3 that lie wholly inside the block
-  for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; ++t) {
-    step(t, s_t, T_{}, I1{}, I2{}, F_{});
-    rp += step_bytes;
-    s_t = s_t == NST - 1 ? 0 : s_t + 1;
-  }
-  for (; t + 3 < nsub; ++t) {
-    step(t, s_t, T_{}, I2{}, I2{}, F_{});
-    s_t = s_t == NST - 1 ? 0 : s_t + 1;
-  }
-  if (t + 2 < nsub) {
-    step(t, s_t, T_{}, I0{}, I1{}, F_{});
-    ++t;
-    s_t = s_t == NST - 1 ? 0 : s_t + 1;
-  }
-  if (t + 1 < nsub) {
-    if (c.r0 + (t + 2) * SR > c.r1) step(t, s_t, T_{}, I0{}, I0{}, T_{});
-    else step(t, s_t, T_{}, I0{}, I0{}, F_{});
-    ++t;
-    s_t = s_t == NST - 1 ? 0 : s_t + 1;
-  }
-  step(t, s_t, F_{}, I0{}, I0{}, F_{});
+  auto run = [&](auto prod_c) __attribute__((always_inline)) {
+    constexpr bool PROD = decltype(prod_c)::value;
+    const char* rp = rp0;
+    auto step = [&](int64_t t, int s_t, auto more_c, auto issue_c, auto later_c, auto tail_c) __attribute__((always_inline)) {
+      constexpr bool MORE = decltype(more_c)::value;
+      constexpr int ISSUE = decltype(issue_c)::value;  // 0: none, 1: inside the block, 2: clamped
+      constexpr int LATER = decltype(later_c)::value;
+      constexpr bool TAIL = decltype(tail_c)::value;
+      const int s_next = s_t == NST - 1 ? 0 : s_t + 1;  // stage of t + 1
+      if constexpr (ISSUE == 1) c.issue_inside(s_t, rp);  // t + 3 lands in the stage of t
+      if constexpr (ISSUE == 2) c.issue(t + 3);
+      Ops o;
+      if constexpr (PROD) load_ops<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, o);
+      if constexpr (MORE) {
+        c.template wait_dma<LATER>();
+        c.fetch(s_next, raw);
+      }
+      if constexpr (PROD) mma_ops(o, L);
+      if constexpr (MORE) c.template digitize<TAIL>(t + 1, raw);
+      if constexpr (PROD && MORE) {
+        // one product, then a share of the conversion, nine times
+#pragma unroll
+        for (int i = 0; i < 9; ++i) {
+          __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+          __builtin_amdgcn_sched_group_barrier(0x002, DIAG ? 4 : 8, 0);
+        }
+      }
+      lds_barrier();
+    };
+    int64_t t = 0;
+    int s_t = 0;  // t % NST
+    // sub-steps t + 3 that lie wholly inside the block
+    for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; ++t) {
+      step(t, s_t, T_{}, I1{}, I2{}, F_{});
+      rp += step_bytes;
+      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+    }
+    for (; t + 3 < nsub; ++t) {
+      step(t, s_t, T_{}, I2{}, I2{}, F_{});
+      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+    }
+    if (t + 2 < nsub) {
+      step(t, s_t, T_{}, I0{}, I1{}, F_{});
+      ++t;
+      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+    }
+    if (t + 1 < nsub) {
+      if (c.r0 + (t + 2) * SR > c.r1) step(t, s_t, T_{}, I0{}, I0{}, T_{});
+      else step(t, s_t, T_{}, I0{}, I0{}, F_{});
+      ++t;
+      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+    }
+    step(t, s_t, F_{}, I0{}, I0{}, F_{});
+  };
+  if (nt) run(T_{});
+  else run(F_{});
 
   // ---- tiles: levels combined, scaled by the grids, into the record ----
   const int p = a.p;
