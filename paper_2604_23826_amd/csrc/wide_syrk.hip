@@ -85,9 +85,6 @@ constexpr int RW = 32 / NW;          // rows per wave per sub-step
 constexpr int MT = 1;                // tiles per wave
 constexpr int G = wide::kSyrkGroup;  // vector columns per group
 constexpr int SR = 32;               // rows per sub-step (K of one product)
-constexpr int NST = 3;               // stages in the LDS ring
-constexpr int RAWB = SR * 2 * G * 4; // row bytes per stage (32 rows x 256 FP32)
-constexpr int STB = RAWB;            // stage bytes
 constexpr int PITCH_MAX = 2 * G + 8;
 constexpr int NSAMP = 1024;          // rows sampled per block for the grids
 constexpr int SB = 16;               // sampled rows per wave in flight
@@ -109,8 +106,6 @@ struct Shape {
   static constexpr int NC = DIAG ? G : 2 * G;  // staged columns
   static constexpr int CPL = NC / 64;           // columns converted per lane
   static constexpr int PITCH = NC + 8;          // dwords per 4-row group (4 PITCH = 32 mod 64 banks)
-  static constexpr int RB = NC * 4;             // bytes per staged row
-  static constexpr int NROW = DIAG ? RW / 2 : RW;  // row DMA instructions per wave per sub-step
 };
 
 // Tiles (ti, tj) of a wave, at most MT; off-diagonal pairs: tile row w.
@@ -146,32 +141,6 @@ __device__ inline WaveTiles wave_tiles(int w, int half) {
     default: r.n = 0; r.ti[0] = 0; r.tj[0] = 0; break;
   }
   return r;
-}
-
-// LDS reads of the DMA target, each in one asm block with its own completion
-// wait: the compiler would otherwise make them wait for every DMA in flight.
-template <int RBYTES>
-__device__ inline void raw_read4(uint32_t a, fl4 (&x)[4]) {
-  static_assert(RBYTES == 1024, "off-diagonal rows");
-  asm volatile(
-      "ds_read_b128 %0, %4\n\t"
-      "ds_read_b128 %1, %4 offset:1024\n\t"
-      "ds_read_b128 %2, %4 offset:2048\n\t"
-      "ds_read_b128 %3, %4 offset:3072\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
-      : "v"(a));
-}
-
-__device__ inline void raw_read2(uint32_t a, fl2 (&x)[4]) {
-  asm volatile(
-      "ds_read_b64 %0, %4\n\t"
-      "ds_read_b64 %1, %4 offset:512\n\t"
-      "ds_read_b64 %2, %4 offset:1024\n\t"
-      "ds_read_b64 %3, %4 offset:1536\n\t"
-      "s_waitcnt lgkmcnt(0)"
-      : "=&v"(x[0]), "=&v"(x[1]), "=&v"(x[2]), "=&v"(x[3])
-      : "v"(a));
 }
 
 // Barrier after this wave's LDS writes, without waiting for the DMA loads in
@@ -223,9 +192,7 @@ struct Ctx {
   static constexpr int NC = Shape<DIAG>::NC;
   static constexpr int CPL = Shape<DIAG>::CPL;
   static constexpr int PITCH = Shape<DIAG>::PITCH;
-  static constexpr int RB = Shape<DIAG>::RB;
   const wide::SyrkArgs& a;
-  unsigned char* ring;  // LDS stages (DMA target only)
   int* dig;             // LDS digits [2][3][8][PITCH]
   const float* s_sc;    // 2^s per staged column (0: not converted)
   const float* s_nks;   // -K 2^s
@@ -239,90 +206,42 @@ struct Ctx {
   // global vector column of staged column c
   __device__ __attribute__((always_inline)) int gcol(int c) const { return DIAG ? A * G + c : (c < G ? A * G + c : B * G + (c - G)); }
 
-  // DMA of this wave's rows of sub-step t into stage t % NST: a fixed number of instructions, every lane active on the
-  // row loads (rows past the block end read its last row, columns past F
-  // read column 0; both are ignored).
-  __device__ __attribute__((always_inline)) void issue(int64_t t) const {
-    const int64_t rb = r0 + t * SR + RW * wave;
-    unsigned char* stage = ring + (int)(t % NST) * STB;  // prologue and last sub-steps only
-    unsigned char* dst = stage + RW * wave * RB;
-    if constexpr (DIAG) {
-      const int dc = A * G + 4 * (lane & 31);
-      const int64_t col = dc < a.F ? dc : 0;
-#pragma unroll
-      for (int m = 0; m < RW / 2; ++m) {
-        int64_t r = rb + 2 * m + h;
-        r = r < r1 ? r : r1 - 1;
-        __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * col),
-                                         (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
-      }
-    } else {
-      const int dc = gcol(4 * lane);
-      const int64_t col = dc < a.F ? dc : 0;
-#pragma unroll
-      for (int j = 0; j < RW; ++j) {
-        int64_t r = rb + j;
-        r = r < r1 ? r : r1 - 1;
-        __builtin_amdgcn_global_load_lds((const void*)(a.xbase + r * a.xstride + 4 * col),
-                                         (__attribute__((address_space(3))) void*)(dst + j * RB), 16, 0, 0);
-      }
-    }
-  }
-
-  // The same DMA for a sub-step that lies inside the block: the lane's row
-  // pointer is advanced by the caller (rp: this wave's first row of the
-  // sub-step, at the lane's column), no clamps.
-  __device__ __attribute__((always_inline)) void issue_inside(int stage_i, const char* rp) const {
-    unsigned char* stage = ring + stage_i * STB;
-    unsigned char* dst = stage + RW * wave * RB;
-    if constexpr (DIAG) {
-#pragma unroll
-      for (int m = 0; m < RW / 2; ++m)
-        __builtin_amdgcn_global_load_lds((const void*)(rp + 2 * m * a.xstride),
-                                         (__attribute__((address_space(3))) void*)(dst + 2 * m * RB), 16, 0, 0);
-    } else {
-#pragma unroll
-      for (int j = 0; j < RW; ++j)
-        __builtin_amdgcn_global_load_lds((const void*)(rp + j * a.xstride),
-                                         (__attribute__((address_space(3))) void*)(dst + j * RB), 16, 0, 0);
-    }
-  }
-
-  // waits until the DMA of the oldest sub-step in flight has landed, with
-  // LATER (0, 1, 2) sub-steps issued after it
-  template <int LATER>
-  __device__ __attribute__((always_inline)) void wait_dma() const {
-    __builtin_amdgcn_s_waitcnt(VmWait<LATER * Shape<DIAG>::NROW>::imm);
-  }
-
-  __device__ __attribute__((always_inline)) uint32_t lds(const void* p) const { return (uint32_t)(uintptr_t)p; }
-
-  // Raw values of one sub-step for this lane: CPL columns x RW rows.
+  // Raw values of one sub-step for this lane: RW rows x CPL columns.
   struct Raw {
     float x[RW][CPL];
   };
 
-  // LDS reads of stage t (its DMA has landed)
-  __device__ __attribute__((always_inline)) void fetch(int stage_i, Raw& r) const {
-    const uint32_t st = lds(ring) + (uint32_t)(stage_i * STB);
+  // Loads of this wave's rows of sub-step t, straight into registers: CPL
+  // consecutive columns of each row per lane (rows past the block end read
+  // its last row, columns past F read column 0; both are ignored).
+  __device__ __attribute__((always_inline)) void load(int64_t t, Raw& r) const {
+    const int64_t rb = r0 + t * SR + RW * wave;
+    const int dc = gcol(cl0);
+    const int64_t col = dc < a.F ? dc : 0;
 #pragma unroll
-    for (int g = 0; g < RW / 4; ++g) {
-      const uint32_t ad = st + (uint32_t)((RW * wave + 4 * g) * RB + 4 * cl0);
-      if constexpr (DIAG) {
-        fl2 v[4];
-        raw_read2(ad, v);
+    for (int j = 0; j < RW; ++j) {
+      int64_t row = rb + j;
+      row = row < r1 ? row : r1 - 1;
+      load_row(a.xbase + row * a.xstride + 4 * col, r.x[j]);
+    }
+  }
+
+  // The same for a sub-step that lies inside the block: rp is this lane's
+  // address in the wave's first row of the sub-step (advanced by the caller).
+  __device__ __attribute__((always_inline)) void load_inside(const char* rp, Raw& r) const {
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
+    for (int j = 0; j < RW; ++j) load_row(rp + j * a.xstride, r.x[j]);
+  }
+
+  __device__ __attribute__((always_inline)) static void load_row(const char* p, float (&x)[CPL]) {
+    if constexpr (CPL == 4) {
+      const fl4 v = *(const fl4*)p;
 #pragma unroll
-          for (int i = 0; i < CPL; ++i) r.x[4 * g + j][i] = v[j][i];
-      } else {
-        fl4 v[4];
-        raw_read4<RB>(ad, v);
+      for (int i = 0; i < 4; ++i) x[i] = v[i];
+    } else {
+      const fl2 v = *(const fl2*)p;
 #pragma unroll
-        for (int j = 0; j < 4; ++j)
-#pragma unroll
-          for (int i = 0; i < CPL; ++i) r.x[4 * g + j][i] = v[j][i];
-      }
+      for (int i = 0; i < 2; ++i) x[i] = v[i];
     }
   }
 
@@ -410,7 +329,6 @@ __device__ inline void mma_ops(const Ops& o, i16 (&L)[MT][5]) {
 }
 
 struct Lds {
-  unsigned char* ring;
   int* dig;
   double* red;      // [NW][256], shares memory with dig
   int* s_exp;
@@ -427,7 +345,6 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   constexpr int NC = Shape<DIAG>::NC;
   constexpr int CPL = Shape<DIAG>::CPL;
   Ctx<DIAG> c(a);
-  c.ring = m.ring;
   c.dig = m.dig;
   c.s_sc = m.s_sc;
   c.s_nks = m.s_nks;
@@ -446,9 +363,10 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   const int tid = threadIdx.x;
   uint64_t* out = a.rec + b * rec_words(a.p);
 
-  c.issue(0);
-  if (nsub > 1) c.issue(1);
-  if (nsub > 2) c.issue(2);
+  // rows of sub-steps 0 and 1 in flight during the sampling
+  typename Ctx<DIAG>::Raw rs[2];
+  c.load(0, rs[0]);
+  if (nsub > 1) c.load(1, rs[1]);
   // ---- shifts; grids from NSAMP rows spread over the block ----
   for (int k = tid; k < NC; k += kThreads) {
     const int g = c.gcol(k);
@@ -530,8 +448,7 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
   }
   lds_barrier();
   if (m.s_flag[0]) {
-    // the whole block is recomputed in FP64; drain the row DMA first
-    c.template wait_dma<0>();
+    // the whole block is recomputed in FP64
     if (tid == 0) a.ovf[b] = 1;
     return;
   }
@@ -551,53 +468,42 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
 #pragma unroll
     for (int l = 0; l < 5; ++l) L[u][l] = (i16){};
 
-  typename Ctx<DIAG>::Raw raw;
-  if (nsub > 2) c.template wait_dma<2>();
-  else if (nsub > 1) c.template wait_dma<1>();
-  else c.template wait_dma<0>();
-  c.fetch(0, raw);
-  if (SR > nrow) c.template digitize<true>(0, raw);
-  else c.template digitize<false>(0, raw);
+  if (SR > nrow) c.template digitize<true>(0, rs[0]);
+  else c.template digitize<false>(0, rs[0]);
   lds_barrier();
-  // Sub-step t: DMA of t + 3 into the stage of t (fetched into registers
-  // one sub-step ago), operands of t, fetch of t + 1 (its DMA was issued two
-  // sub-steps ago), products of t and digits of t + 1, interleaved so that
-  // the conversion's vector instructions issue while the matrix cores work.
-  // Branch-free in the main loop; the last three sub-steps are peeled.  Waves
-  // without a tile run the same loop without the products (same barriers).
-  // row pointers of sub-step t + 3 for the DMA inside the block
+  // Sub-step t: loads of t + 2 into the registers of t (converted one
+  // sub-step ago), operands of t, products of t and digits of t + 1 (loaded
+  // one sub-step ago), interleaved so that the conversion's vector
+  // instructions issue while the matrix cores work.  Register sets
+  // alternate, so the main loop takes two sub-steps per trip; the last
+  // sub-steps run one at a time.  Waves without a tile run the same loop
+  // without the products (same barriers).
   const int64_t step_bytes = (int64_t)SR * a.xstride;
-  const char* rp0;
+  const char* rp0;  // this lane's address in the wave's first row of sub-step 2
   {
-    const int dc = DIAG ? A * G + 4 * (c.lane & 31) : c.gcol(4 * c.lane);
+    const int dc = c.gcol(c.cl0);
     const int64_t col = dc < a.F ? dc : 0;
-    const int64_t r = c.r0 + 3 * SR + RW * c.wave + (DIAG ? c.h : 0);
-    rp0 = a.xbase + r * a.xstride + 4 * col;
+    rp0 = a.xbase + (c.r0 + 2 * SR + RW * c.wave) * a.xstride + 4 * col;
   }
   using T_ = std::true_type;
   using F_ = std::false_type;
   using I0 = std::integral_constant<int, 0>;
   using I1 = std::integral_constant<int, 1>;
-  using I2 = std::integral_constant<int, 2>;
   auto run = [&](auto prod_c) __attribute__((always_inline)) {
     constexpr bool PROD = decltype(prod_c)::value;
     const char* rp = rp0;
-    auto step = [&](int64_t t, int s_t, auto more_c, auto issue_c, auto later_c, auto tail_c) __attribute__((always_inline)) {
+    // PAR = t & 1; LOAD: 0 none, 1 inside the block (rp), 2 clamped
+    auto step = [&](int64_t t, auto par_c, auto load_c, auto more_c, auto tail_c) __attribute__((always_inline)) {
+      constexpr int PAR = decltype(par_c)::value;
+      constexpr int LOAD = decltype(load_c)::value;
       constexpr bool MORE = decltype(more_c)::value;
-      constexpr int ISSUE = decltype(issue_c)::value;  // 0: none, 1: inside the block, 2: clamped
-      constexpr int LATER = decltype(later_c)::value;
       constexpr bool TAIL = decltype(tail_c)::value;
-      const int s_next = s_t == NST - 1 ? 0 : s_t + 1;  // stage of t + 1
-      if constexpr (ISSUE == 1) c.issue_inside(s_t, rp);  // t + 3 lands in the stage of t
-      if constexpr (ISSUE == 2) c.issue(t + 3);
+      if constexpr (LOAD == 1) c.load_inside(rp, rs[PAR]);
+      if constexpr (LOAD == 2) c.load(t + 2, rs[PAR]);
       Ops o;
-      if constexpr (PROD) load_ops<DIAG>(m.dig, (int)(t & 1), wt, c.h, c.q, o);
-      if constexpr (MORE) {
-        c.template wait_dma<LATER>();
-        c.fetch(s_next, raw);
-      }
+      if constexpr (PROD) load_ops<DIAG>(m.dig, PAR, wt, c.h, c.q, o);
       if constexpr (PROD) mma_ops(o, L);
-      if constexpr (MORE) c.template digitize<TAIL>(t + 1, raw);
+      if constexpr (MORE) c.template digitize<TAIL>(t + 1, rs[PAR ^ 1]);
       if constexpr (PROD && MORE) {
         // one product, then a share of the conversion, nine times
 #pragma unroll
@@ -609,29 +515,26 @@ __device__ __attribute__((always_inline)) void pair_block(const wide::SyrkArgs& 
       lds_barrier();
     };
     int64_t t = 0;
-    int s_t = 0;  // t % NST
-    // sub-steps t + 3 that lie wholly inside the block
-    for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; ++t) {
-      step(t, s_t, T_{}, I1{}, I2{}, F_{});
+    // pairs of sub-steps whose loads (t + 2, t + 3) lie wholly inside the block
+    for (; t + 3 < nsub && c.r0 + (t + 4) * SR <= c.r1; t += 2) {
+      step(t, I0{}, I1{}, T_{}, F_{});
       rp += step_bytes;
-      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+      step(t + 1, I1{}, I1{}, T_{}, F_{});
+      rp += step_bytes;
     }
-    for (; t + 3 < nsub; ++t) {
-      step(t, s_t, T_{}, I2{}, I2{}, F_{});
-      s_t = s_t == NST - 1 ? 0 : s_t + 1;
-    }
-    if (t + 2 < nsub) {
-      step(t, s_t, T_{}, I0{}, I1{}, F_{});
-      ++t;
-      s_t = s_t == NST - 1 ? 0 : s_t + 1;
+    // the rest one by one: loads clamped to the block, rows past its end
+    // give zero digits
+    for (; t + 2 < nsub; ++t) {
+      if (t & 1) step(t, I1{}, std::integral_constant<int, 2>{}, T_{}, T_{});
+      else step(t, I0{}, std::integral_constant<int, 2>{}, T_{}, T_{});
     }
     if (t + 1 < nsub) {
-      if (c.r0 + (t + 2) * SR > c.r1) step(t, s_t, T_{}, I0{}, I0{}, T_{});
-      else step(t, s_t, T_{}, I0{}, I0{}, F_{});
+      if (t & 1) step(t, I1{}, I0{}, T_{}, T_{});
+      else step(t, I0{}, I0{}, T_{}, T_{});
       ++t;
-      s_t = s_t == NST - 1 ? 0 : s_t + 1;
     }
-    step(t, s_t, F_{}, I0{}, I0{}, F_{});
+    if (t & 1) step(t, I1{}, I0{}, F_{}, F_{});
+    else step(t, I0{}, I0{}, F_{}, F_{});
   };
   if (nt) run(T_{});
   else run(F_{});
@@ -890,7 +793,6 @@ __global__ __launch_bounds__(kSumThreads, 3) void k_syrk_sums(wide::SyrkArgs a) 
 }
 
 __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
-  __shared__ __attribute__((aligned(16))) unsigned char s_ring[NST * STB];
   __shared__ __attribute__((aligned(16))) union {
     int dig[2 * 3 * 8 * PITCH_MAX];
     double red[NW * 2 * G];
@@ -905,7 +807,6 @@ __global__ __launch_bounds__(kThreads, 1) void k_syrk_i8(wide::SyrkArgs a) {
   if (b >= a.nblocks) return;
   const int A = a.pairs[t].x & 15, B = a.pairs[t].y, half = a.pairs[t].x >> 4;
   Lds m;
-  m.ring = s_ring;
   m.dig = s_u.dig;
   m.red = s_u.red;
   m.s_exp = s_exp;
