@@ -457,9 +457,9 @@ def run_wide(args, L, torch, datagen):
     sp = res["split"]
     # algorithmic work per row: 1028 bytes read; p(p+1) = 2T flops (the upper
     # triangle of x x^T).  The split kernel issues nine int8 digit products
-    # on 32 x 32 tiles: 48 tile products per row of 256 columns (3 group
-    # pairs x 2 halves x 8 waves; the diagonal pairs' 10 tiles in 16 wave
-    # slots), 9 x 2 x 48 x 1024 integer operations per row
+    # on 32 x 32 tiles: the 36 upper tiles of 256 columns (3 group pairs x 2
+    # halves; waves of a diagonal half without a tile skip the products),
+    # 9 x 2 x 36 x 1024 integer operations per row
     bytes_row = 4 * 256 + 4
     launches = max(sp["launches_per_pass"], 1)
     out = base_json(args, N / (sp["accumulate_ms"] / 1e3), "rows/s", sp["accumulate_ms"], "i8x3",
@@ -471,12 +471,12 @@ def run_wide(args, L, torch, datagen):
                                    sp["syrk_ms"], int(round(launches)), N * bytes_row / launches,
                                    traffic_from_profile(N / launches, "wide"))
     algo = 2.0 * N * T / (sp["syrk_ms"] / 1e3) / 1e12
-    issued = 9 * 2 * 48 * 1024 * N / (sp["syrk_ms"] / 1e3) / 1e12
+    issued = 9 * 2 * 36 * 1024 * N / (sp["syrk_ms"] / 1e3) / 1e12
     out["roofline"]["mfma"] = {"algorithmic_tflops": round(algo, 1),
                                "issued_int8_tops": round(issued, 1),
                                "issued_frac_of_int8_peak": round(issued / I8_PEAK_TOPS, 4),
                                "algorithmic_flops_per_row": 2 * T,
-                               "issued_int8_ops_per_row": 9 * 2 * 48 * 1024}
+                               "issued_int8_ops_per_row": 9 * 2 * 36 * 1024}
     out["hbm_gbs"] = round(N * 1028 / (sp["accumulate_ms"] / 1e3) / 1e9, 1)
     out["fp64_path"] = {"accumulate_ms": round(res["fp64"]["accumulate_ms"], 2),
                         "syrk_ms": round(res["fp64"]["syrk_ms"], 2),

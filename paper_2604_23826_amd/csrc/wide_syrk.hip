@@ -45,25 +45,28 @@
 // Work split: vector columns form groups of 128.  A workgroup owns one block
 // of rows and one half of a pair of groups (A, B), A <= B: two tile rows of
 // A for an off-diagonal pair (8 tiles), tile rows {0, 3} or {1, 2} of a
-// diagonal one (5 upper tiles).  Eight waves, two per SIMD, with one 32 x 32
-// tile each (its five int32 levels in 80 accumulation registers), so that
-// each wave's waits are covered by the other wave of its SIMD.  The sums stay
-// out of this pass: in the workgroups of the diagonal pairs they would double
-// the vector work on the pass's critical path.  Workgroup ids put all
-// pairs of one block on the same XCD (ids congruent modulo 8), so the block's
-// rows come from HBM once and from that XCD's L2 after.
+// diagonal one (5 upper tiles; its other three waves only load and convert).
+// Eight waves, two per SIMD, with at most one 32 x 32 tile each (its five
+// int32 levels in 80 accumulation registers), so that each wave's waits are
+// covered by the other wave of its SIMD.  The sums stay out of this pass: in
+// the workgroups of the diagonal pairs they would double the vector work on
+// the pass's critical path.  Workgroup ids put all pairs of one block on the
+// same XCD (ids congruent modulo 8), so that a block's rows can come from
+// that XCD's L2 for the pairs after the first (the two halves of a pair, which
+// run at the same speed, do share them; pairs of different kinds drift apart).
 //
-// Data path per 32-row sub-step: each wave moves its own four rows from HBM
-// into an LDS ring of three stages by
-// direct DMA (global_load_lds, two sub-steps in flight) and converts exactly
-// those rows, so its only wait on the ring is its own vector-memory counter.
-// The digits go to a double-buffered LDS array, [digit][4-row group][column]
-// as dwords of four rows; one barrier per sub-step separates the conversion
-// of sub-step t + 1 from the products of sub-step t.  The K index of a
-// product is the row, so a lane's operand dwords j = 0..3 are its column's
-// row groups 4h + j.  The conversion of sub-step t + 1 and the products of
-// sub-step t are independent, so the compiler interleaves the vector work
-// into the matrix-core shadow.
+// Data path per 32-row sub-step: each wave loads its own four rows (a lane
+// four consecutive columns of each, two on a diagonal half) from global
+// memory straight into
+// registers, two alternating register sets, one sub-step ahead, and converts
+// exactly those rows.  The digits go to a double-buffered LDS array,
+// [digit][4-row group][column] as dwords of four rows; one barrier per
+// sub-step separates the conversion of sub-step t + 1 from the products of
+// sub-step t.  The K index of a product is the row, so a lane's operand
+// dwords j = 0..3 are its column's row groups 4h + j.  The conversion of
+// sub-step t + 1 and the products of sub-step t are independent; the
+// schedule interleaves them (one product, then a share of the conversion),
+// so the vector work issues while the matrix cores run.
 #include <type_traits>
 
 #include "common.hpp"
