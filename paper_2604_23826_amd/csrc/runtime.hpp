@@ -70,8 +70,10 @@ struct stats_ctx {
   uint64_t* seg_part = nullptr;  // partial states of the segmented merge's first stage
   size_t seg_part_cap = 0;
 
-  // text ingest: bytes consumed so far (offsets in parse errors)
+  // text ingest: bytes consumed so far (offsets in parse errors), and the
+  // mean line length of the last chunk measured (0: none yet)
   int64_t text_offset = 0;
+  double text_ell = 0.0;
 
   // kernel timing (STATS_CFG_TIMING)
   std::vector<std::pair<hipEvent_t, hipEvent_t>> pending[STATS_K_COUNT];

@@ -7,11 +7,13 @@
 // sums and X^T X accumulators as the binary path; nothing is written back.
 //
 // Work split: workgroup w owns the lines whose first byte lies in
-// [w * SEG, (w + 1) * SEG); within it, thread t owns the lines starting in its
-// 256-byte slice.  The workgroup stages its bytes (plus MAXLINE bytes of the
-// next segment, for lines that run past the end) in LDS with 16 bytes of
-// padding per 256, so that threads reading their own slices hit different
-// banks.  The block shift is the workgroup's first line.
+// [w seg, (w + 1) seg), seg a multiple of 4096 up to 40 KiB chosen per chunk
+// from its mean line length (pick_text_seg); its threads find the line starts
+// of seg / 256-byte slices, then take the lines in turn, one per thread and
+// round.  The workgroup stages its bytes (plus MAXLINE bytes of the next
+// segment, for lines that run past the end) in LDS with 16 bytes of padding
+// per 256, so that threads reading their own slices hit different banks.  The
+// block shift is the workgroup's first line.
 //
 // Fields: integer columns are decimal integers (optional sign, at most 18
 // digits), parsed exactly; other columns are decimal numbers (optional sign,
@@ -23,6 +25,7 @@
 // q < -57 is refused as malformed (in between, by the significand's bit
 // length).  A malformed field marks
 // the handle (STATS_E_PARSE, smallest byte offset) and its row is skipped.
+#include <cmath>
 #include <cstring>
 
 #include "accum_common.hpp"
@@ -34,11 +37,13 @@ namespace text {
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kThreads = 256;
-constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup
+constexpr int SEG = 1 << 15;     // bytes of line starts per workgroup (conversion, line counts)
+constexpr int SEG_MAX = 40 << 10;  // the fused kernel's segments: a multiple of 4096 up to this (chosen per chunk)
 constexpr int MAXLINE = 4096;    // longest line accepted
 constexpr int SLICE = SEG / 256;  // bytes of line starts per thread (one slice per thread)
+constexpr int SLICE_MAX = SEG_MAX / 256;
 constexpr int MAXLS = 2048;      // line starts per workgroup kept in the table
-constexpr int STAGE = 32 + SEG + MAXLINE;  // + up to 15 bytes of alignment in front
+constexpr int STAGE = 32 + SEG_MAX + MAXLINE;  // + up to 15 bytes of alignment in front
 constexpr int STAGE_PADDED = STAGE + (STAGE / 256 + 2) * 16;  // room for word reads past the end
 
 struct Args {
@@ -48,6 +53,7 @@ struct Args {
   int p;
   uint32_t intmask;
   int64_t base_off;  // offset of buf in the caller's stream (for messages)
+  int seg;           // bytes of line starts per workgroup: a multiple of 4096, at most SEG_MAX
   acc::Args acc;
   DevStatus* status;
 };
@@ -594,20 +600,21 @@ __device__ inline int stage_text(const char* buf, int64_t w0r, int nr, unsigned 
 
 // Line starts of a workgroup's segment [s0r, s1r) (stage-relative; a line
 // starts after '\n' or at the stream start).  Thread t finds the newlines of
-// its SLICE positions in one pass of 16-byte LDS reads, keeping them as a bit
+// its slice (slice positions, a multiple of 16 up to SLICE_MAX) in one pass
+// of 16-byte LDS reads, keeping them as a bit
 // mask (a '\n' byte is a zero byte of v ^ 0x0a0a0a0a); a workgroup scan of the
 // counts places them in s_ls in stream order when they fit (<= MAXLS).
 // Returns their number; *c0, *c1 receive this thread's slice and *before the
 // number of line starts in earlier slices (the index of its first line).
 // Contains barriers: every thread of the workgroup calls it.
-__device__ inline int line_starts(const unsigned char* s_buf, int64_t w0, int s0r, int s1r,
+__device__ inline int line_starts(const unsigned char* s_buf, int64_t w0, int s0r, int s1r, int slice,
                                   unsigned short* s_ls, int* s_wsum, int* c0_out, int* c1_out,
                                   int* before_out) {
-  static_assert(SLICE * kThreads == SEG && SLICE % 16 == 0, "one slice per thread");
-  constexpr int NV = SLICE / 16 + 1;         // 16-byte reads per slice (it may start mid-vector)
+  static_assert(SLICE * kThreads == SEG && SLICE % 16 == 0 && SLICE_MAX % 16 == 0, "one slice per thread");
+  constexpr int NV = SLICE_MAX / 16 + 1;     // 16-byte reads per slice (it may start mid-vector)
   constexpr int NM = (16 * NV + 31) / 32;    // 32-bit mask words
-  const int c0 = s0r + (int)threadIdx.x * SLICE;
-  const int c1 = min(c0 + SLICE, s1r);
+  const int c0 = s0r + (int)threadIdx.x * slice;
+  const int c1 = min(c0 + slice, s1r);
   // newline positions m in [mlo, mhi) start the lines c0 .. c1 - 1; bit b of the
   // mask is position mb + b
   const int mlo = max(c0 - 1, 0), mhi = c1 - 1;
@@ -703,8 +710,8 @@ __global__ __launch_bounds__(kThreads, 2) void k_text(Args a) {
   __shared__ unsigned short s_ls[MAXLS];  // line starts (stage-relative)
   __shared__ int s_wsum[NWV];
   static_assert(STAGE_PADDED >= NWV * 5 * 64 * 8, "the final reduction reuses the text stage");
-  const int64_t s0 = (int64_t)blockIdx.x * SEG;
-  const int64_t s1 = min(s0 + (int64_t)SEG, a.nend);
+  const int64_t s0 = (int64_t)blockIdx.x * a.seg;
+  const int64_t s1 = min(s0 + (int64_t)a.seg, a.nend);
   const int64_t w0r = s0 >= 16 ? s0 - 16 : 0;  // first stream byte staged
   const int64_t w1 = min(s1 + (int64_t)MAXLINE, a.nbytes);
   // w0: stream offset of LDS position 0 (the staging origin is aligned)
@@ -717,7 +724,7 @@ __global__ __launch_bounds__(kThreads, 2) void k_text(Args a) {
   Cur C(S);
 
   int c0, c1, before;
-  const int total = line_starts(s_buf, w0, s0r, s1r, s_ls, s_wsum, &c0, &c1, &before);
+  const int total = line_starts(s_buf, w0, s0r, s1r, a.seg / kThreads, s_ls, s_wsum, &c0, &c1, &before);
   (void)before;
   const bool table = total <= MAXLS;
 
@@ -864,6 +871,30 @@ __global__ void k_last_newline(const char* buf, int64_t n, int64_t* out) {
   if (threadIdx.x == 0) *out = (int64_t)best;
 }
 
+// Newlines in a sample of [0, n), 64 windows: the 64 equal parts of it up
+// to 1 MiB, else 16 KiB at the start of each 64th.  Workgroup k (1024
+// threads, 16 bytes each, all loads in flight at once) writes the count of
+// window k to out[k].  The chunk's mean line length sets the fused kernel's
+// segment size.
+constexpr int kDensWin = 64;
+constexpr int kDensBytes = 16 << 10;
+__global__ __launch_bounds__(1024) void k_line_density(const char* buf, int64_t n, int64_t* out) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  const int k = blockIdx.x;
+  const bool all = n <= (int64_t)kDensWin * kDensBytes;
+  const int64_t lo = all ? n * k / kDensWin : (n / kDensWin) * k;
+  const int64_t hi = all ? n * (k + 1) / kDensWin : lo + kDensBytes;
+  const int64_t i0 = lo + 16 * (int64_t)threadIdx.x;
+  int c = 0;
+#pragma unroll
+  for (int u = 0; u < 16; ++u) c += (i0 + u < hi && buf[i0 + u] == '\n') ? 1 : 0;
+  atomicAdd(&cnt, c);
+  __syncthreads();
+  if (threadIdx.x == 0) out[k] = cnt;
+}
+
 // ---- CSV -> fixed-width binary rows ------------------------------------------
 
 // Line starts per segment ([s0, s1) as in k_text), read from global memory.
@@ -964,7 +995,7 @@ __global__ __launch_bounds__(kThreads) void k_text_convert(ConvArgs a) {
   const int s0r = (int)(s0 - w0), s1r = (int)(s1 - w0);
   Cur C(S);
   int c0, c1, before;
-  const int total = line_starts(s_buf, w0, s0r, s1r, s_ls, s_wsum, &c0, &c1, &before);
+  const int total = line_starts(s_buf, w0, s0r, s1r, SLICE, s_ls, s_wsum, &c0, &c1, &before);
   const int64_t base = a.seg_base[blockIdx.x];
   int first_bad = INT32_MAX;
   // parses line L (k-th of the segment) into output row base + k
@@ -1010,9 +1041,37 @@ void launch_text_p(const Args& a, int64_t nblocks, hipStream_t s) {
 
 using namespace text;
 
+// Segment size of the fused kernel for lines of mean length ell bytes.  A
+// workgroup parses its lines 256 at a time (one per thread); the last round
+// runs with the lanes that still have a line, and the workgroup holds its
+// compute unit until then, so a segment whose line count just passes a
+// multiple of 256 wastes most of a round.  Each multiple of 4096 from 16 KiB
+// to SEG_MAX is scored as the filled share of its rounds (its count taken 3 %
+// high for the spread between segments) times seg / (seg + 4.8 KiB) (the
+// fixed cost of a workgroup: the staged overlap, the line table, the final
+// sums and the record), halved when the lines would overflow the line table
+// (MAXLS; its fallback scans slices); the best one is used.  Without a
+// measurement: 32 KiB.
+static int pick_text_seg(double ell) {
+  if (!(ell > 0.0)) return SEG;
+  int best = SEG;
+  double best_score = -1.0;
+  for (int seg = 16 << 10; seg <= SEG_MAX; seg += 4096) {
+    const double lines = seg / ell;
+    const double rounds = std::ceil(lines * 1.03 / kThreads);
+    const double score = lines / (rounds * kThreads) * seg / (seg + 4915.0) * (lines * 1.03 <= MAXLS ? 1.0 : 0.5);
+    if (score > best_score) {
+      best_score = score;
+      best = seg;
+    }
+  }
+  return best;
+}
+
 static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t nend, int64_t base_off) {
   const int p = h->p;
-  const int64_t nblocks = (nend + SEG - 1) / SEG;
+  const int seg = pick_text_seg(h->text_ell);
+  const int64_t nblocks = (nend + seg - 1) / seg;
   if (nblocks == 0) return STATS_OK;
   const int64_t W = rec_words(p);
   int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
@@ -1024,6 +1083,7 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   a.nend = nend;
   a.p = p;
   a.base_off = base_off;
+  a.seg = seg;
   a.status = h->status_dev;
   uint32_t intmask = 0;
   for (int c = 0; c < p; ++c)
@@ -1097,16 +1157,28 @@ extern "C" int stats_accumulate_text(stats_ctx* h, const char* buf, int64_t nbyt
     return fail(STATS_E_ARG, "unknown mem_kind");
   }
   int64_t nend = nbytes;
-  if (!is_last) {
-    int rc = ensure_dev(h, (void**)&h->raw_out, &h->raw_cap, 64);
+  // the last line end of a chunk that is not the last one, and the chunk's
+  // line density (every chunk that waits for the first anyway, and a last
+  // chunk when nothing was measured before)
+  if (!is_last || !(h->text_ell > 0.0)) {
+    int rc = ensure_dev(h, (void**)&h->raw_out, &h->raw_cap, 8 * (1 + kDensWin));
     if (rc) return rc;
-    hipLaunchKernelGGL(k_last_newline, dim3(1), dim3(1024), 0, h->stream, dbuf, nbytes,
-                       (int64_t*)h->raw_out);
+    int64_t* ro = (int64_t*)h->raw_out;
+    if (!is_last) hipLaunchKernelGGL(k_last_newline, dim3(1), dim3(1024), 0, h->stream, dbuf, nbytes, ro);
+    hipLaunchKernelGGL(k_line_density, dim3(kDensWin), dim3(1024), 0, h->stream, dbuf, nbytes, ro + 1);
     e = hipGetLastError();
+    int64_t hv[1 + kDensWin];
+    hv[0] = nbytes;
     if (e == hipSuccess)
-      e = hipMemcpyAsync(&nend, h->raw_out, 8, hipMemcpyDeviceToHost, h->stream);
+      e = hipMemcpyAsync(is_last ? hv + 1 : hv, is_last ? ro + 1 : ro, 8 * (is_last ? kDensWin : 1 + kDensWin),
+                         hipMemcpyDeviceToHost, h->stream);
     if (e == hipSuccess) e = hipStreamSynchronize(h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "finding the last line end");
+    nend = hv[0];
+    int64_t lines = 0;
+    for (int k = 1; k <= kDensWin; ++k) lines += hv[k];
+    const int64_t counted = nbytes <= (int64_t)kDensWin * kDensBytes ? nbytes : (int64_t)kDensWin * kDensBytes;
+    if (lines > 0) h->text_ell = (double)counted / (double)lines;
   }
   const int64_t base_off = h->text_offset;
   int rc = text_launch(h, dbuf, nbytes, nend, base_off);
