@@ -143,6 +143,38 @@ def test_short_lines_and_digit_runs():
     check_raw_against_oracle(raw, st, [True, False])
 
 
+@pytest.mark.parametrize("width", [1, 10, 18, 25, 40])
+def test_line_lengths_set_the_segment_size(width):
+    """The fused kernel's segment size follows the chunk's sampled mean line
+    length (lines of 25 to 100 bytes on average here pick segments of 24, 28,
+    32, 36 and 40 KiB): each size parses three zero-padded integer columns and
+    one decimal column, over two chunks, to the oracle's statistics."""
+    L = lib()
+    rng = np.random.default_rng(width)
+    n = 120_000
+    a = rng.integers(-9, 10, n)
+    b = rng.integers(0, 10 ** 4, n)
+    c = rng.normal(0.0, 1e3, n)
+    fmt_a = b"%0" + str(width).encode() + b"d"
+    lines = [fmt_a % x + b"," + (b"%d" % y).rjust(width, b"0") + b"," + (b"%d" % (i + 1)) + b"," + (b"%.6f" % z)
+             + b"\n" for i, (x, y, z) in enumerate(zip(a, b, c))]
+    txt = b"".join(lines)
+    int_cols = [True, True, True, False]
+    rows = oracle.parse_csv(txt, 4, int_cols)
+    h = L.stats_open(_cfg(L, p=4, int_cols=int_cols))
+    try:
+        d = _text_dev(txt)
+        half = len(txt) // 2
+        used = L.stats_accumulate_text(h, d.data_ptr(), half, is_last=False)
+        used += L.stats_accumulate_text(h, d.data_ptr() + used, len(txt) - used, is_last=True)
+        assert used == len(txt)
+        raw = L.stats_raw(h, 4)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(rows), int_cols)
+    check_raw_against_oracle(raw, st, int_cols)
+
+
 def test_parse_errors_report_offsets():
     L = lib()
     good = b"1,2,3\n"
