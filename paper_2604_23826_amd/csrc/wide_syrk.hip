@@ -595,6 +595,7 @@ constexpr int kSumRPW = 4;                    // rows per wave and stage
 constexpr int kSumNS = 3;                     // stages per wave
 constexpr int kSumSB = kSumRPW * 1024 + 64;   // stage bytes: rows + extras' words
 
+template <int NS>  // the number of extra columns (a.ne)
 __global__ __launch_bounds__(kSumThreads, 3) void k_syrk_sums(wide::SyrkArgs a) {
   constexpr int NQ = NE * (NE + 1) / 2;
   constexpr int NW4 = kSumThreads / 64;
@@ -609,7 +610,7 @@ __global__ __launch_bounds__(kSumThreads, 3) void k_syrk_sums(wide::SyrkArgs a) 
   const int64_t r0 = b * a.R, r1 = min(r0 + a.R, a.nrows);
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int ne = cb == 0 ? a.ne : 0;  // the extras' own sums: first chunk
-  const int ns = a.ne;                 // strips with the extras: every chunk
+  constexpr int ns = NS;               // strips with the extras: every chunk
   const int c0 = cb + 4 * lane;
   const bool cv = c0 < F;  // F is a multiple of 4
   float K[4], lim[4], sc[4];
@@ -723,16 +724,17 @@ __global__ __launch_bounds__(kSumThreads, 3) void k_syrk_sums(wide::SyrkArgs a) 
         const double d = (double)d32;
         S[i] += d;
 #pragma unroll
-        for (int e = 0; e < NE; ++e) ST[e][i] = __builtin_fma(d, de[e], ST[e][i]);
+        for (int e = 0; e < NS; ++e) ST[e][i] = __builtin_fma(d, de[e], ST[e][i]);
         fo = fmaxf(fo, __builtin_amdgcn_fractf(x * sc[i]));
         over |= !(fabsf(d32) <= lim[i]);
       }
       int q = 0;
 #pragma unroll
       for (int e = 0; e < NE; ++e) {
-        es[e] += de[e];
+        if (e < NS) es[e] += de[e];
 #pragma unroll
-        for (int g = e; g < NE; ++g, ++q) eq[q] = __builtin_fma(de[e], de[g], eq[q]);
+        for (int g = e; g < NE; ++g, ++q)
+          if (g < NS) eq[q] = __builtin_fma(de[e], de[g], eq[q]);
       }
     }
   }
@@ -834,7 +836,12 @@ void launch_syrk_split(const wide::SyrkArgs& a, hipStream_t s) {
   const int64_t nb8 = (a.nblocks + 7) / 8 * 8;
   hipLaunchKernelGGL(syrk::k_syrk_i8, dim3((unsigned)(nb8 * a.npairs)), dim3(syrk::kThreads), 0, s, a);
   const int64_t nch = (a.F + 255) / 256;
-  hipLaunchKernelGGL(syrk::k_syrk_sums, dim3((unsigned)(a.nblocks * nch)), dim3(syrk::kSumThreads), 0, s, a);
+  const dim3 gs((unsigned)(a.nblocks * nch));
+  switch (a.ne) {
+    case 0: hipLaunchKernelGGL(syrk::k_syrk_sums<0>, gs, dim3(syrk::kSumThreads), 0, s, a); break;
+    case 1: hipLaunchKernelGGL(syrk::k_syrk_sums<1>, gs, dim3(syrk::kSumThreads), 0, s, a); break;
+    default: hipLaunchKernelGGL(syrk::k_syrk_sums<2>, gs, dim3(syrk::kSumThreads), 0, s, a); break;
+  }
 }
 
 }  // namespace st
