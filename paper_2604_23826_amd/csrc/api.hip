@@ -396,7 +396,7 @@ static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t 
   while (done < nrows) {
     const int64_t rows = std::min(nrows - done, max_rows);
     const int64_t nblocks = (rows + R - 1) / R;
-    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)((nblocks * W + merge_slice_words(nblocks, p)) * 8));
     if (rc) return rc;
     for (int c = 0; c < p; ++c) {
       const stats_column& col = h->cols[c];
@@ -434,7 +434,7 @@ static int accumulate_aos_rows(stats_ctx* h, const void* const* planes, int64_t 
       Timer t;
       t.begin(h, STATS_K_MERGE);
       launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1],
-                           h->status_dev, h->stream);
+                           h->status_dev, h->stream, h->rec + nblocks * W);
       t.end();
     }
     e = hipGetLastError();
@@ -482,7 +482,7 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
   while (done < nrows) {
     const int64_t rows = std::min(nrows - done, max_rows);
     const int64_t nblocks = (rows + R - 1) / R;
-    int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)((nblocks * W + merge_slice_words(nblocks, p)) * 8));
     if (rc) return rc;
     AccumLaunch b = a;
     for (int c = 0; c < p; ++c) b.colbase[c] = a.colbase[c] + done * a.colstride[c];
@@ -500,7 +500,8 @@ int accumulate_device_small(stats_ctx* h, const void* const* planes, int64_t nro
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
-      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1],
+                           h->status_dev, h->stream, h->rec + nblocks * W);
       t.end();
     }
     e = hipGetLastError();

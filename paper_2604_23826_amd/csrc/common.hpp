@@ -390,8 +390,13 @@ struct AccumLaunch {
 int64_t launch_accum_small_p(const AccumLaunch& a, hipStream_t s);
 
 // Merge nblocks records into the state: cur -> next (double-buffered).
+// With part (merge_slice_words(nblocks, p) words of device memory, when that
+// is not 0) many records are folded in slices by several workgroups per
+// entry, then the slice totals in order; without it, in one pass per entry.
 void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intflags_dev,
-                          const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s);
+                          const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s,
+                          uint64_t* part = nullptr);
+int64_t merge_slice_words(int64_t nblocks, int p);
 
 // dst status |= src status (stream-ordered; see k_status_or).
 void launch_status_or(DevStatus* dst, const DevStatus* src, hipStream_t s);

@@ -110,120 +110,243 @@ __global__ __launch_bounds__(kThreads) void k_merge_l2(const uint64_t* __restric
   }
 }
 
-// Records -> state in one pass: one workgroup per entry.  Thread t folds
-// blocks t, t + 256, ... in order (the words of eight of them loaded before
-// the first is folded), then the 256 partial results are combined
-// by a fixed binary tree in LDS (Chan update + exact 128-bit sums) and the
-// total is merged into the current state (cur -> next).  The tree shape is
-// fixed, so the result is deterministic.
+// Records -> state.  One workgroup per entry (and, in the split form, per
+// slice of the records): thread t folds records lo + t, lo + t + 256, ...
+// below hi in order (the words of eight of them loaded before the first is
+// folded), then the 256 partial results are combined by a fixed binary tree
+// in LDS (Chan update + exact 128-bit sums).  The tree shape and the slices
+// are fixed, so the result is deterministic.
 constexpr int kTreeThreads = 256;
 
+struct Tree {
+  double n[kTreeThreads], mi[kTreeThreads], mj[kTreeThreads], m2[kTreeThreads];
+  uint64_t lo[kTreeThreads], hi[kTreeThreads];
+};
+
+struct Entry {
+  int i, j;
+  bool is_col, ii, ij;
+  int64_t t;  // packed-triangle index of (i, j); of (i, i) for a column
+};
+
+__device__ inline Entry entry_of(int p, int64_t e, const uint8_t* intf) {
+  Entry E;
+  entry_cols(p, e, &E.i, &E.j, &E.is_col);
+  E.ii = intf[E.i];
+  E.ij = intf[E.j];
+  E.t = E.is_col ? tri(p, E.i, E.i) : e - p;
+  return E;
+}
+
+// One block record's words (n_b, flags, K_i, K_j, S_i, S_j, Q_ij) folded
+// into an entry's running total.
+__device__ inline void fold_one(const uint64_t* wd, const Entry& E, Chan& acc, i128& exact,
+                                uint32_t& inexact) {
+  const int64_t nb = (int64_t)wd[0];
+  if (nb == 0) return;
+  const double nbd = (double)nb;
+  const uint64_t Kiw = wd[2], Kjw = wd[3];
+  const double Si = __longlong_as_double((long long)wd[4]);
+  const double Sj = __longlong_as_double((long long)wd[5]);
+  const double Qij = __longlong_as_double((long long)wd[6]);
+  Chan blk;
+  blk.n = nbd;
+  blk.mi = kval(Kiw, E.ii) + Si / nbd;
+  blk.mj = kval(Kjw, E.ij) + Sj / nbd;
+  blk.m2 = E.is_col ? 0.0 : Qij - Si * (Sj / nbd);
+  chan_add(acc, blk);
+  if (E.is_col && E.ii) {
+    const int64_t K = (int64_t)Kiw;
+    if (wd[1] != 0 || !(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
+    exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
+  } else if (!E.is_col && E.ii && E.ij) {
+    const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
+    exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
+  }
+}
+
+__device__ inline void load_rec_words(const uint64_t* r, int p, const Entry& E, uint64_t* wd) {
+  wd[1] = r[1];
+  wd[2] = r[2 + E.i];
+  wd[3] = r[2 + E.j];
+  wd[4] = r[2 + p + E.i];
+  wd[5] = r[2 + p + E.j];
+  wd[6] = r[2 + 2 * p + E.t];
+}
+
+// Leaves the entry's total over records [lo, hi) in slot 0 of S (all
+// threads of the workgroup take part; S is valid after the last barrier).
+__device__ void fold_records(const uint64_t* __restrict__ rec, int64_t lo, int64_t hi, int p,
+                             const Entry& E, DevStatus* status, Tree& S) {
+  const int64_t W = rec_words(p);
+  Chan acc = {0.0, 0.0, 0.0, 0.0};
+  i128 exact = 0;
+  uint32_t inexact = 0;
+  constexpr int kU = 8;
+  for (int64_t b0 = lo + threadIdx.x; b0 < hi; b0 += kTreeThreads * kU) {
+    uint64_t wd[kU][7];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t b = b0 + (int64_t)u * kTreeThreads;
+      const uint64_t* r = rec + (b < hi ? b : lo) * W;
+      wd[u][0] = b < hi ? r[0] : 0;
+      load_rec_words(r, p, E, wd[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u) fold_one(wd[u], E, acc, exact, inexact);
+  }
+  if (inexact) atomicOr(&status->bits, ST_INEXACT);
+  const int tid = threadIdx.x;
+  S.n[tid] = acc.n;
+  S.mi[tid] = acc.mi;
+  S.mj[tid] = acc.mj;
+  S.m2[tid] = acc.m2;
+  S.lo[tid] = (uint64_t)(u128)exact;
+  S.hi[tid] = (uint64_t)((u128)exact >> 64);
+  __syncthreads();
+  for (int s = kTreeThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      Chan a = {S.n[tid], S.mi[tid], S.mj[tid], S.m2[tid]};
+      const Chan b = {S.n[tid + s], S.mi[tid + s], S.mj[tid + s], S.m2[tid + s]};
+      chan_add(a, b);
+      S.n[tid] = a.n;
+      S.mi[tid] = a.mi;
+      S.mj[tid] = a.mj;
+      S.m2[tid] = a.m2;
+      const uint64_t w0[2] = {S.lo[tid], S.hi[tid]}, w1[2] = {S.lo[tid + s], S.hi[tid + s]};
+      const i128 sum = load_i128(w0) + load_i128(w1);
+      S.lo[tid] = (uint64_t)(u128)sum;
+      S.hi[tid] = (uint64_t)((u128)sum >> 64);
+    }
+    __syncthreads();
+  }
+}
+
+// next = cur followed by the records' total (add, add_exact) for entry e.
+__device__ void finish_entry(int p, int64_t e, const Entry& E, const Chan& add, i128 add_exact,
+                             const uint64_t* __restrict__ cur, uint64_t* __restrict__ next) {
+  const Layout L = Layout::make(p);
+  Chan tot = chan_of(cur, L, E.i, E.j, E.is_col ? -1 : E.t);
+  chan_add(tot, add);
+  if (E.is_col) {
+    store_i128(next + L.off_s + 2 * E.i, load_i128(cur + L.off_s + 2 * E.i) + add_exact);
+    next[L.off_mu + E.i] = (uint64_t)__double_as_longlong(tot.mi);
+    if (e == 0) {
+      next[0] = (uint64_t)((int64_t)cur[0] + (int64_t)add.n);
+      next[1] = 0;
+    }
+  } else {
+    const i128 base = load_i128(cur + L.off_C + 2 * E.t);
+    store_i128(next + L.off_C + 2 * E.t, (E.ii && E.ij) ? base + add_exact : base);
+    next[L.off_M2 + E.t] = (uint64_t)__double_as_longlong(tot.m2);
+  }
+}
+
+// One pass over all records per entry (few records, or many entries).
 __global__ __launch_bounds__(kTreeThreads) void k_merge_tree(const uint64_t* __restrict__ rec,
                                                              int64_t nblocks, int p,
                                                              const uint8_t* __restrict__ intf,
                                                              const uint64_t* __restrict__ cur,
                                                              uint64_t* __restrict__ next,
                                                              DevStatus* status) {
-  __shared__ double s_n[kTreeThreads], s_mi[kTreeThreads], s_mj[kTreeThreads], s_m2[kTreeThreads];
-  __shared__ uint64_t s_lo[kTreeThreads], s_hi[kTreeThreads];
-  const Layout L = Layout::make(p);
+  __shared__ Tree S;
   const int64_t e = blockIdx.x;
-  int i, j;
-  bool is_col;
-  entry_cols(p, e, &i, &j, &is_col);
-  const bool ii = intf[i], ij = intf[j];
+  const Entry E = entry_of(p, e, intf);
+  fold_records(rec, 0, nblocks, p, E, status, S);
+  if (threadIdx.x == 0) {
+    const Chan add = {S.n[0], S.mi[0], S.mj[0], S.m2[0]};
+    const uint64_t w[2] = {S.lo[0], S.hi[0]};
+    finish_entry(p, e, E, add, load_i128(w), cur, next);
+  }
+}
+
+// Split form, first stage: workgroup (e, g) folds slice g of the records
+// (slices of `per` consecutive records) and writes its total to
+// part[(e * nslices + g) * 6 ...] as n, mean_i, mean_j, M2 and the two
+// words of the exact sum.
+__global__ __launch_bounds__(kTreeThreads) void k_merge_slices(const uint64_t* __restrict__ rec,
+                                                               int64_t nblocks, int64_t per, int p,
+                                                               const uint8_t* __restrict__ intf,
+                                                               uint64_t* __restrict__ part,
+                                                               DevStatus* status) {
+  __shared__ Tree S;
+  const int64_t e = blockIdx.x;
+  const int64_t g = blockIdx.y;
+  const Entry E = entry_of(p, e, intf);
+  const int64_t lo = g * per;
+  const int64_t hi = lo + per < nblocks ? lo + per : nblocks;
+  fold_records(rec, lo, hi, p, E, status, S);
+  if (threadIdx.x == 0) {
+    uint64_t* o = part + (e * (int64_t)gridDim.y + g) * 6;
+    o[0] = (uint64_t)__double_as_longlong(S.n[0]);
+    o[1] = (uint64_t)__double_as_longlong(S.mi[0]);
+    o[2] = (uint64_t)__double_as_longlong(S.mj[0]);
+    o[3] = (uint64_t)__double_as_longlong(S.m2[0]);
+    o[4] = S.lo[0];
+    o[5] = S.hi[0];
+  }
+}
+
+// Split form for many entries, first stage: thread (e, g) folds slice g of
+// the records for entry e alone (adjacent threads read adjacent words of a
+// record) and writes its total as k_merge_slices does.
+__global__ __launch_bounds__(256) void k_merge_slices_thr(const uint64_t* __restrict__ rec,
+                                                          int64_t nblocks, int64_t per, int p,
+                                                          const uint8_t* __restrict__ intf,
+                                                          uint64_t* __restrict__ part,
+                                                          DevStatus* status) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t g = blockIdx.y;
   const int64_t W = rec_words(p);
-  const int64_t t = is_col ? tri(p, i, i) : e - p;
+  if (e >= p + Layout::make(p).T) return;
+  const Entry E = entry_of(p, e, intf);
+  const int64_t lo = g * per;
+  const int64_t hi = lo + per < nblocks ? lo + per : nblocks;
   Chan acc = {0.0, 0.0, 0.0, 0.0};
   i128 exact = 0;
   uint32_t inexact = 0;
-  // records b, b + 256, ... in order; the words of kU records are loaded
-  // before the first of them is folded
-  constexpr int kU = 8;
-  for (int64_t b0 = threadIdx.x; b0 < nblocks; b0 += kTreeThreads * kU) {
+  constexpr int kU = 4;
+  for (int64_t b0 = lo; b0 < hi; b0 += kU) {
     uint64_t wd[kU][7];
 #pragma unroll
     for (int u = 0; u < kU; ++u) {
-      const int64_t b = b0 + (int64_t)u * kTreeThreads;
-      const uint64_t* r = rec + (b < nblocks ? b : 0) * W;
-      wd[u][0] = b < nblocks ? r[0] : 0;
-      wd[u][1] = r[1];
-      wd[u][2] = r[2 + i];
-      wd[u][3] = r[2 + j];
-      wd[u][4] = r[2 + p + i];
-      wd[u][5] = r[2 + p + j];
-      wd[u][6] = r[2 + 2 * p + t];
+      const int64_t b = b0 + u;
+      const uint64_t* r = rec + (b < hi ? b : lo) * W;
+      wd[u][0] = b < hi ? r[0] : 0;
+      load_rec_words(r, p, E, wd[u]);
     }
 #pragma unroll
-    for (int u = 0; u < kU; ++u) {
-      const int64_t nb = (int64_t)wd[u][0];
-      if (nb == 0) continue;
-      const double nbd = (double)nb;
-      const uint64_t Kiw = wd[u][2], Kjw = wd[u][3];
-      const double Si = __longlong_as_double((long long)wd[u][4]);
-      const double Sj = __longlong_as_double((long long)wd[u][5]);
-      const double Qij = __longlong_as_double((long long)wd[u][6]);
-      Chan blk;
-      blk.n = nbd;
-      blk.mi = kval(Kiw, ii) + Si / nbd;
-      blk.mj = kval(Kjw, ij) + Sj / nbd;
-      blk.m2 = is_col ? 0.0 : Qij - Si * (Sj / nbd);
-      chan_add(acc, blk);
-      if (is_col && ii) {
-        const int64_t K = (int64_t)Kiw;
-        if (wd[u][1] != 0 || !(Qij < kExactQ) || K >= kMaxShift || K <= -kMaxShift) inexact = 1;
-        exact += (i128)(int64_t)Si + (i128)nb * (i128)K;
-      } else if (!is_col && ii && ij) {
-        const i128 Ki = (i128)(int64_t)Kiw, Kj = (i128)(int64_t)Kjw;
-        exact += (i128)(int64_t)Qij + Ki * (i128)(int64_t)Sj + (i128)(int64_t)Si * Kj + (i128)nb * Ki * Kj;
-      }
-    }
+    for (int u = 0; u < kU; ++u) fold_one(wd[u], E, acc, exact, inexact);
   }
   if (inexact) atomicOr(&status->bits, ST_INEXACT);
-  const int tid = threadIdx.x;
-  s_n[tid] = acc.n;
-  s_mi[tid] = acc.mi;
-  s_mj[tid] = acc.mj;
-  s_m2[tid] = acc.m2;
-  s_lo[tid] = (uint64_t)(u128)exact;
-  s_hi[tid] = (uint64_t)((u128)exact >> 64);
-  __syncthreads();
-  for (int s = kTreeThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      Chan a = {s_n[tid], s_mi[tid], s_mj[tid], s_m2[tid]};
-      const Chan b = {s_n[tid + s], s_mi[tid + s], s_mj[tid + s], s_m2[tid + s]};
-      chan_add(a, b);
-      s_n[tid] = a.n;
-      s_mi[tid] = a.mi;
-      s_mj[tid] = a.mj;
-      s_m2[tid] = a.m2;
-      const uint64_t w0[2] = {s_lo[tid], s_hi[tid]}, w1[2] = {s_lo[tid + s], s_hi[tid + s]};
-      const i128 sum = load_i128(w0) + load_i128(w1);
-      s_lo[tid] = (uint64_t)(u128)sum;
-      s_hi[tid] = (uint64_t)((u128)sum >> 64);
-    }
-    __syncthreads();
+  uint64_t* o = part + (e * (int64_t)gridDim.y + g) * 6;
+  o[0] = (uint64_t)__double_as_longlong(acc.n);
+  o[1] = (uint64_t)__double_as_longlong(acc.mi);
+  o[2] = (uint64_t)__double_as_longlong(acc.mj);
+  o[3] = (uint64_t)__double_as_longlong(acc.m2);
+  o[4] = (uint64_t)(u128)exact;
+  o[5] = (uint64_t)((u128)exact >> 64);
+}
+
+// Split form, second stage: entry e's slice totals combined in slice order
+// (Chan update + exact sum), then merged into the state (cur -> next).
+__global__ void k_merge_slices_fold(const uint64_t* __restrict__ part, int nslices, int p,
+                                    const uint8_t* __restrict__ intf,
+                                    const uint64_t* __restrict__ cur, uint64_t* __restrict__ next) {
+  const int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const Layout L = Layout::make(p);
+  if (e >= p + L.T) return;
+  const Entry E = entry_of(p, e, intf);
+  Chan acc = {0.0, 0.0, 0.0, 0.0};
+  i128 exact = 0;
+  for (int g = 0; g < nslices; ++g) {
+    const uint64_t* o = part + (e * nslices + g) * 6;
+    const Chan c = {__longlong_as_double((long long)o[0]), __longlong_as_double((long long)o[1]),
+                    __longlong_as_double((long long)o[2]), __longlong_as_double((long long)o[3])};
+    chan_add(acc, c);
+    exact += load_i128(o + 4);
   }
-  if (tid == 0) {
-    const int64_t tt = is_col ? -1 : t;
-    Chan tot = chan_of(cur, L, i, j, tt);
-    const Chan add = {s_n[0], s_mi[0], s_mj[0], s_m2[0]};
-    chan_add(tot, add);
-    const uint64_t w[2] = {s_lo[0], s_hi[0]};
-    const i128 add_exact = load_i128(w);
-    if (is_col) {
-      store_i128(next + L.off_s + 2 * i, load_i128(cur + L.off_s + 2 * i) + add_exact);
-      next[L.off_mu + i] = (uint64_t)__double_as_longlong(tot.mi);
-      if (e == 0) {
-        next[0] = (uint64_t)((int64_t)cur[0] + (int64_t)s_n[0]);
-        next[1] = 0;
-      }
-    } else {
-      const i128 base = load_i128(cur + L.off_C + 2 * t);
-      store_i128(next + L.off_C + 2 * t, (ii && ij) ? base + add_exact : base);
-      next[L.off_M2 + t] = (uint64_t)__double_as_longlong(tot.m2);
-    }
-  }
+  finish_entry(p, e, E, acc, exact, cur, next);
 }
 
 // Deferred errors of a merged source (exactness guard, text parse) carry
@@ -238,16 +361,66 @@ __global__ void k_status_or(DevStatus* dst, const DevStatus* src) {
 
 }  // namespace
 
+// Slices of the split merge (1: the one-pass form).  Up to 1023 entries a
+// workgroup folds each (entry, slice): enough of them to cover the GPU about
+// three times, each slice at least 2048 records (eight per thread).  From
+// 1024 entries a thread folds each (entry, slice): 64 slices of at least 16
+// records.  At most 64 slices, so an entry's total passes through at most
+// ceil(slice / 256) + 8 + 64 (workgroup form) or slice + 64 (thread form)
+// successive Chan updates.
+struct MergePlan {
+  int64_t g;
+  bool per_thread;
+};
+
+static MergePlan merge_plan(int64_t nblocks, int64_t E) {
+  MergePlan m;
+  m.per_thread = E >= 1024;
+  int64_t g, by_len;
+  if (m.per_thread) {
+    g = 64;
+    by_len = nblocks / 16;
+  } else {
+    g = (768 + E - 1) / E;
+    by_len = nblocks / 2048;
+  }
+  if (g > by_len) g = by_len;
+  if (g > 64) g = 64;
+  m.g = g < 1 ? 1 : g;
+  return m;
+}
+
 void launch_status_or(DevStatus* dst, const DevStatus* src, hipStream_t s) {
   hipLaunchKernelGGL(k_status_or, dim3(1), dim3(64), 0, s, dst, src);
 }
 
+int64_t merge_slice_words(int64_t nblocks, int p) {
+  const int64_t E = p + Layout::make(p).T;
+  const int64_t g = merge_plan(nblocks, E).g;
+  return g > 1 ? E * g * 6 : 0;
+}
+
 void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uint8_t* intf,
-                          const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s) {
+                          const uint64_t* cur, uint64_t* next, DevStatus* status, hipStream_t s,
+                          uint64_t* part) {
   const Layout L = Layout::make(p);
   const int64_t E = p + L.T;
-  hipLaunchKernelGGL(k_merge_tree, dim3((unsigned)E), dim3(kTreeThreads), 0, s, rec, nblocks, p,
-                     intf, cur, next, status);
+  const MergePlan m = merge_plan(nblocks, E);
+  const int64_t g = m.g;
+  if (part == nullptr || g <= 1) {
+    hipLaunchKernelGGL(k_merge_tree, dim3((unsigned)E), dim3(kTreeThreads), 0, s, rec, nblocks, p,
+                       intf, cur, next, status);
+    return;
+  }
+  const int64_t per = (nblocks + g - 1) / g;
+  if (m.per_thread)
+    hipLaunchKernelGGL(k_merge_slices_thr, dim3((unsigned)((E + 255) / 256), (unsigned)g), dim3(256), 0,
+                       s, rec, nblocks, per, p, intf, part, status);
+  else
+    hipLaunchKernelGGL(k_merge_slices, dim3((unsigned)E, (unsigned)g), dim3(kTreeThreads), 0, s, rec,
+                       nblocks, per, p, intf, part, status);
+  hipLaunchKernelGGL(k_merge_slices_fold, dim3((unsigned)((E + 63) / 64)), dim3(64), 0, s, part,
+                     (int)g, p, intf, cur, next);
 }
 
 void launch_merge_states(const uint64_t* a, const uint64_t* b, uint64_t* out, int p,

@@ -1074,7 +1074,9 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   const int64_t nblocks = (nend + seg - 1) / seg;
   if (nblocks == 0) return STATS_OK;
   const int64_t W = rec_words(p);
-  int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+  // block records, then the slice totals of the merge
+  const int64_t part_words = merge_slice_words(nblocks, p);
+  int rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)((nblocks * W + part_words) * 8));
   if (rc) return rc;
   Args a;
   memset(&a, 0, sizeof a);
@@ -1118,7 +1120,8 @@ static int text_launch(stats_ctx* h, const char* dbuf, int64_t nbytes, int64_t n
   {
     Timer t;
     t.begin(h, STATS_K_MERGE);
-    launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream);
+    launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1], h->status_dev, h->stream,
+                         part_words ? h->rec + nblocks * W : nullptr);
     t.end();
   }
   err = hipGetLastError();

@@ -155,7 +155,7 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
     e = hipMemcpyAsync(slots_dev, slots.data(), sizeof(wide::SlotInfo) * (size_t)p, hipMemcpyHostToDevice,
                        h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
-    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)((nblocks * W + merge_slice_words(nblocks, p)) * 8));
     if (rc) return rc;
     a.rec = h->rec;
     a.nblocks = nblocks;
@@ -184,8 +184,8 @@ static int accumulate_syrk(stats_ctx* h, const void* const* planes, int64_t nrow
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
-      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur],
-                           h->state[h->cur ^ 1], h->status_dev, h->stream);
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1],
+                           h->status_dev, h->stream, h->rec + nblocks * W);
       t.end();
     }
     e = hipGetLastError();
@@ -240,7 +240,7 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
     // the previous launch has read the table before this copy is ordered after it
     e = hipMemcpyAsync(slots_dev, slots.data(), slot_bytes, hipMemcpyHostToDevice, h->stream);
     if (e != hipSuccess) return hip_fail(h, e, "uploading slot table");
-    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)(nblocks * W * 8));
+    rc = ensure_dev(h, (void**)&h->rec, &h->rec_cap, (size_t)((nblocks * W + merge_slice_words(nblocks, p)) * 8));
     if (rc) return rc;
     wide::Args a;
     a.slots = slots_dev;
@@ -263,8 +263,8 @@ int accumulate_device_wide(stats_ctx* h, const void* const* planes, int64_t nrow
     {
       Timer t;
       t.begin(h, STATS_K_MERGE);
-      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur],
-                           h->state[h->cur ^ 1], h->status_dev, h->stream);
+      launch_merge_records(h->rec, nblocks, p, h->intf_dev, h->state[h->cur], h->state[h->cur ^ 1],
+                           h->status_dev, h->stream, h->rec + nblocks * W);
       t.end();
     }
     e = hipGetLastError();
