@@ -1,0 +1,96 @@
+"""GPU parity of the sliced block-record merge against the CPU oracle.
+
+Launches with many block records fold them in fixed slices (a workgroup per
+entry and slice below 1024 entries, a thread per entry and slice from 1024
+entries), then the slice totals in slice order.  The sizes below are chosen
+so that each form runs with several slices and a ragged last slice: integer
+columns stay bit-exact, floating ones within the usual tolerance, and the
+exactness guard is still raised from a record in the last slice."""
+import numpy as np
+import pytest
+
+import datagen
+import oracle
+from datagen import gauss
+from helpers import (TABLE1_INT, aos_config, check_final_against_oracle, check_raw_against_oracle,
+                     corr_scaled_err, current_stream, lib, to_dev)
+
+pytestmark = pytest.mark.gpu
+
+SEL = list(range(1, 10))  # identifier excluded
+
+
+def test_workgroup_slices_table1():
+    # 1024-row blocks: 8204 records in one launch (65 entries), four slices of
+    # 2051 records, the last block ragged
+    n = 8_400_001
+    print(f"sliced merge, workgroup form: aos n={n}", flush=True)
+    L = lib()
+    x = datagen.table1_aos(41, n)
+    h = L.stats_open(aos_config(stream=current_stream(), block_rows=1024))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], n)
+        raw = L.stats_raw(h, 10)
+        fin = L.stats_finalize(h, 10)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(x), TABLE1_INT, threads=8)
+    check_raw_against_oracle(raw, st, TABLE1_INT)
+    check_final_against_oracle(fin, oracle.finalize(st, mask=SEL), [TABLE1_INT[c] for c in SEL])
+
+
+def test_workgroup_slices_report_inexact_from_last_slice():
+    # 4200 records: two slices of 2100; the fraction sits in block 4195
+    n = 4_300_003
+    print(f"sliced merge, inexact in the last slice: aos n={n}", flush=True)
+    L = lib()
+    x = datagen.table1_aos(42, n)
+    x[n - 5000, 3] += 0.5  # D declared integer but holds a fraction
+    h = L.stats_open(aos_config(stream=current_stream(), block_rows=1024))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], n)
+        with pytest.raises(L.StatsError) as e:
+            L.stats_sync(h)
+        assert e.value.code == L.STATS_E_INEXACT
+    finally:
+        L.stats_close(h)
+
+
+def _c3_config(L, p, **kw):
+    # column 0: int32 identifier (plane 1); columns 1..p-1: FP32 row-major (plane 0)
+    cols = [(L.STATS_I32, 1, 0, L.STATS_COL_IDENTIFIER)] + \
+           [(L.STATS_F32, 0, 4 * j, 0) for j in range(p - 1)]
+    return L.make_config(cols, [4 * (p - 1), 4], stream=current_stream(), **kw)
+
+
+@pytest.mark.parametrize("prec", ["fp64", "split"])
+def test_thread_slices_wide(prec):
+    # p = 65: 2210 entries; 4096-row blocks, 49 records: three slices of 17,
+    # the last one shorter and its last block ragged
+    p, n = 65, 200_003
+    print(f"sliced merge, thread form: p={p} n={n} {prec}", flush=True)
+    L = lib()
+    x = gauss.rows_host(43, n, p - 1)
+    ident = np.arange(1, n + 1, dtype=np.int32)
+    precision = L.STATS_PREC_FP64 if prec == "fp64" else L.STATS_PREC_SPLIT
+    h = L.stats_open(_c3_config(L, p, precision=precision, block_rows=4096))
+    try:
+        L.stats_accumulate(h, [to_dev(x), to_dev(ident)], n)
+        raw = L.stats_raw(h, p)
+        fin = L.stats_finalize(h, p)
+    finally:
+        L.stats_close(h)
+    is_int = [True] + [False] * (p - 1)
+    st = oracle.sufficient_stats([ident] + [x[:, j] for j in range(p - 1)], is_int, threads=8)
+    assert raw["n"] == n
+    assert raw["s_int"][0] == n * (n + 1) // 2
+    assert raw["C_int"][0][0] == n * (n + 1) * (2 * n + 1) // 6
+    ref = oracle.finalize(st, mask=range(1, p))
+    tol = 1e-12 if prec == "fp64" else 1e-9
+    err = corr_scaled_err(fin["cov"], ref["cov"])
+    print(f"  cov err {err:.2e}", flush=True)
+    assert err <= tol
+    check_final_against_oracle(fin, ref, [False] * (p - 1), tol=tol)
+    for j in range(1, p):
+        ref_c = float(st.C_exact[oracle.tri_index(p, 0, j)])
+        assert abs(raw["C_f64"][0, j] - ref_c) <= 1e-9 * abs(ref_c)
