@@ -138,6 +138,29 @@ __device__ inline Entry entry_of(int p, int64_t e, const uint8_t* intf) {
   return E;
 }
 
+// The fixed binary tree over the 256 slots of S (Chan update + exact sums);
+// called after the slots are written and a barrier; slot 0 holds the total
+// after it returns.
+__device__ void tree_reduce(Tree& S) {
+  const int tid = threadIdx.x;
+  for (int s = kTreeThreads / 2; s > 0; s >>= 1) {
+    if (tid < s) {
+      Chan a = {S.n[tid], S.mi[tid], S.mj[tid], S.m2[tid]};
+      const Chan b = {S.n[tid + s], S.mi[tid + s], S.mj[tid + s], S.m2[tid + s]};
+      chan_add(a, b);
+      S.n[tid] = a.n;
+      S.mi[tid] = a.mi;
+      S.mj[tid] = a.mj;
+      S.m2[tid] = a.m2;
+      const uint64_t w0[2] = {S.lo[tid], S.hi[tid]}, w1[2] = {S.lo[tid + s], S.hi[tid + s]};
+      const i128 sum = load_i128(w0) + load_i128(w1);
+      S.lo[tid] = (uint64_t)(u128)sum;
+      S.hi[tid] = (uint64_t)((u128)sum >> 64);
+    }
+    __syncthreads();
+  }
+}
+
 // One block record's words (n_b, flags, K_i, K_j, S_i, S_j, Q_ij) folded
 // into an entry's running total.
 __device__ inline void fold_one(const uint64_t* wd, const Entry& E, Chan& acc, i128& exact,
@@ -204,22 +227,7 @@ __device__ void fold_records(const uint64_t* __restrict__ rec, int64_t lo, int64
   S.lo[tid] = (uint64_t)(u128)exact;
   S.hi[tid] = (uint64_t)((u128)exact >> 64);
   __syncthreads();
-  for (int s = kTreeThreads / 2; s > 0; s >>= 1) {
-    if (tid < s) {
-      Chan a = {S.n[tid], S.mi[tid], S.mj[tid], S.m2[tid]};
-      const Chan b = {S.n[tid + s], S.mi[tid + s], S.mj[tid + s], S.m2[tid + s]};
-      chan_add(a, b);
-      S.n[tid] = a.n;
-      S.mi[tid] = a.mi;
-      S.mj[tid] = a.mj;
-      S.m2[tid] = a.m2;
-      const uint64_t w0[2] = {S.lo[tid], S.hi[tid]}, w1[2] = {S.lo[tid + s], S.hi[tid + s]};
-      const i128 sum = load_i128(w0) + load_i128(w1);
-      S.lo[tid] = (uint64_t)(u128)sum;
-      S.hi[tid] = (uint64_t)((u128)sum >> 64);
-    }
-    __syncthreads();
-  }
+  tree_reduce(S);
 }
 
 // next = cur followed by the records' total (add, add_exact) for entry e.
@@ -328,6 +336,132 @@ __global__ __launch_bounds__(256) void k_merge_slices_thr(const uint64_t* __rest
   o[5] = (uint64_t)((u128)exact >> 64);
 }
 
+// Split form for few entries (at most 256), first stage: workgroup g folds
+// slice g.  Each of its four waves takes every fourth record of the slice and
+// each lane the entries lane, lane + 64, ... (adjacent lanes read adjacent
+// words of a record, so a record is read once per wave); the four waves'
+// totals are then combined per entry in wave order and written out as
+// k_merge_slices does.
+constexpr int kLanesMaxE = 256;
+
+// KK = ceil(entries / 64) entries per lane; the words of kU records per
+// wave are loaded before the first of them is folded.
+template <int KK>
+__global__ __launch_bounds__(256) void k_merge_slices_lanes(const uint64_t* __restrict__ rec,
+                                                            int64_t nblocks, int64_t per, int p,
+                                                            const uint8_t* __restrict__ intf,
+                                                            uint64_t* __restrict__ part,
+                                                            DevStatus* status) {
+  __shared__ double s_n[4][kLanesMaxE], s_mi[4][kLanesMaxE], s_mj[4][kLanesMaxE], s_m2[4][kLanesMaxE];
+  __shared__ uint64_t s_lo[4][kLanesMaxE], s_hi[4][kLanesMaxE];
+  const int E = p + (int)Layout::make(p).T;
+  const int lane = threadIdx.x & 63, w = threadIdx.x >> 6;
+  const int64_t g = blockIdx.x;
+  const int64_t W = rec_words(p);
+  const int64_t lo = g * per;
+  const int64_t hi = lo + per < nblocks ? lo + per : nblocks;
+  constexpr int kK = KK;
+  constexpr int kU = KK <= 2 ? 4 : 2;
+  Entry en[kK];
+  Chan acc[kK];
+  i128 ex[kK];
+  bool has[kK];
+  uint32_t inexact = 0;
+#pragma unroll
+  for (int k = 0; k < kK; ++k) {
+    const int e = lane + 64 * k;
+    has[k] = e < E;
+    en[k] = entry_of(p, has[k] ? e : 0, intf);
+    acc[k] = Chan{0.0, 0.0, 0.0, 0.0};
+    ex[k] = 0;
+  }
+  // wave w folds records lo + w, lo + w + 4, ... in order
+  for (int64_t b0 = lo + w; b0 < hi; b0 += 4 * kU) {
+    uint64_t wd[kU][kK][7];
+#pragma unroll
+    for (int u = 0; u < kU; ++u) {
+      const int64_t b = b0 + 4 * u;
+      const uint64_t* r = rec + (b < hi ? b : lo) * W;
+#pragma unroll
+      for (int k = 0; k < kK; ++k) {
+        wd[u][k][0] = (b < hi && has[k]) ? r[0] : 0;
+        load_rec_words(r, p, en[k], wd[u][k]);
+      }
+    }
+#pragma unroll
+    for (int u = 0; u < kU; ++u)
+#pragma unroll
+      for (int k = 0; k < kK; ++k) fold_one(wd[u][k], en[k], acc[k], ex[k], inexact);
+  }
+  if (inexact) atomicOr(&status->bits, ST_INEXACT);
+#pragma unroll
+  for (int k = 0; k < kK; ++k) {
+    const int e = lane + 64 * k;
+    if (e < E) {
+      s_n[w][e] = acc[k].n;
+      s_mi[w][e] = acc[k].mi;
+      s_mj[w][e] = acc[k].mj;
+      s_m2[w][e] = acc[k].m2;
+      s_lo[w][e] = (uint64_t)(u128)ex[k];
+      s_hi[w][e] = (uint64_t)((u128)ex[k] >> 64);
+    }
+  }
+  __syncthreads();
+  const int e = threadIdx.x;
+  if (e < E) {
+    Chan a = {s_n[0][e], s_mi[0][e], s_mj[0][e], s_m2[0][e]};
+    i128 x = (i128)(((u128)s_hi[0][e] << 64) | (u128)s_lo[0][e]);
+    for (int v = 1; v < 4; ++v) {
+      const Chan b = {s_n[v][e], s_mi[v][e], s_mj[v][e], s_m2[v][e]};
+      chan_add(a, b);
+      x += (i128)(((u128)s_hi[v][e] << 64) | (u128)s_lo[v][e]);
+    }
+    uint64_t* o = part + ((int64_t)e * (int64_t)gridDim.x + g) * 6;
+    o[0] = (uint64_t)__double_as_longlong(a.n);
+    o[1] = (uint64_t)__double_as_longlong(a.mi);
+    o[2] = (uint64_t)__double_as_longlong(a.mj);
+    o[3] = (uint64_t)__double_as_longlong(a.m2);
+    o[4] = (uint64_t)(u128)x;
+    o[5] = (uint64_t)((u128)x >> 64);
+  }
+}
+
+// Second stage for many slices: one workgroup per entry; thread t folds the
+// slice totals t, t + 256, ... in order, then the fixed LDS tree, then the
+// total is merged into the state (cur -> next).
+__global__ __launch_bounds__(kTreeThreads) void k_merge_slices_tree(const uint64_t* __restrict__ part,
+                                                                    int64_t nslices, int p,
+                                                                    const uint8_t* __restrict__ intf,
+                                                                    const uint64_t* __restrict__ cur,
+                                                                    uint64_t* __restrict__ next) {
+  __shared__ Tree S;
+  const int64_t e = blockIdx.x;
+  const Entry E = entry_of(p, e, intf);
+  Chan acc = {0.0, 0.0, 0.0, 0.0};
+  i128 exact = 0;
+  for (int64_t g = threadIdx.x; g < nslices; g += kTreeThreads) {
+    const uint64_t* o = part + (e * nslices + g) * 6;
+    const Chan c = {__longlong_as_double((long long)o[0]), __longlong_as_double((long long)o[1]),
+                    __longlong_as_double((long long)o[2]), __longlong_as_double((long long)o[3])};
+    chan_add(acc, c);
+    exact += load_i128(o + 4);
+  }
+  const int tid = threadIdx.x;
+  S.n[tid] = acc.n;
+  S.mi[tid] = acc.mi;
+  S.mj[tid] = acc.mj;
+  S.m2[tid] = acc.m2;
+  S.lo[tid] = (uint64_t)(u128)exact;
+  S.hi[tid] = (uint64_t)((u128)exact >> 64);
+  __syncthreads();
+  tree_reduce(S);
+  if (tid == 0) {
+    const Chan add = {S.n[0], S.mi[0], S.mj[0], S.m2[0]};
+    const uint64_t w[2] = {S.lo[0], S.hi[0]};
+    finish_entry(p, e, E, add, load_i128(w), cur, next);
+  }
+}
+
 // Split form, second stage: entry e's slice totals combined in slice order
 // (Chan update + exact sum), then merged into the state (cur -> next).
 __global__ void k_merge_slices_fold(const uint64_t* __restrict__ part, int nslices, int p,
@@ -361,7 +495,10 @@ __global__ void k_status_or(DevStatus* dst, const DevStatus* src) {
 
 }  // namespace
 
-// Slices of the split merge (1: the one-pass form).  Up to 1023 entries a
+// Slices of the split merge (1: the one-pass form).  Up to 256 entries and
+// from 8192 records, a workgroup folds each slice of 64 records for all
+// entries (lanes hold entries), and the slice totals are folded by a tree.
+// Otherwise, up to 1023 entries a
 // workgroup folds each (entry, slice): enough of them to cover the GPU about
 // three times, each slice at least 2048 records (eight per thread).  From
 // 1024 entries a thread folds each (entry, slice): 64 slices of at least 16
@@ -371,10 +508,18 @@ __global__ void k_status_or(DevStatus* dst, const DevStatus* src) {
 struct MergePlan {
   int64_t g;
   bool per_thread;
+  bool lanes;
 };
 
 static MergePlan merge_plan(int64_t nblocks, int64_t E) {
   MergePlan m;
+  m.lanes = false;
+  if (E <= kLanesMaxE && nblocks >= 8192) {
+    m.per_thread = false;
+    m.lanes = true;
+    m.g = (nblocks + 63) / 64;
+    return m;
+  }
   m.per_thread = E >= 1024;
   int64_t g, by_len;
   if (m.per_thread) {
@@ -413,6 +558,18 @@ void launch_merge_records(const uint64_t* rec, int64_t nblocks, int p, const uin
     return;
   }
   const int64_t per = (nblocks + g - 1) / g;
+  if (m.lanes) {
+    const dim3 grid((unsigned)g), block(256);
+    switch ((E + 63) / 64) {
+      case 1: hipLaunchKernelGGL(k_merge_slices_lanes<1>, grid, block, 0, s, rec, nblocks, per, p, intf, part, status); break;
+      case 2: hipLaunchKernelGGL(k_merge_slices_lanes<2>, grid, block, 0, s, rec, nblocks, per, p, intf, part, status); break;
+      case 3: hipLaunchKernelGGL(k_merge_slices_lanes<3>, grid, block, 0, s, rec, nblocks, per, p, intf, part, status); break;
+      default: hipLaunchKernelGGL(k_merge_slices_lanes<4>, grid, block, 0, s, rec, nblocks, per, p, intf, part, status); break;
+    }
+    hipLaunchKernelGGL(k_merge_slices_tree, dim3((unsigned)E), dim3(kTreeThreads), 0, s, part, g, p, intf,
+                       cur, next);
+    return;
+  }
   if (m.per_thread)
     hipLaunchKernelGGL(k_merge_slices_thr, dim3((unsigned)((E + 255) / 256), (unsigned)g), dim3(256), 0,
                        s, rec, nblocks, per, p, intf, part, status);
