@@ -124,3 +124,27 @@ def test_workgroup_slices_wide():
     print(f"  cov err {err:.2e}", flush=True)
     assert err <= 1e-12
     check_final_against_oracle(fin, ref, [False] * (p - 1), tol=1e-12)
+
+
+@pytest.mark.parametrize("p", [5, 16, 20])
+def test_lane_slices_entries_per_lane(p):
+    # 15, 136 and 210 pairs (20, 152 and 230 entries: one, three and four
+    # entries per lane); integer-valued FP64 rows with one Gaussian column,
+    # 1024-row blocks: 8204 records in 129 lane slices
+    n = 8_400_001
+    print(f"sliced merge, lanes form: p={p} n={n}", flush=True)
+    L = lib()
+    x = np.random.default_rng(p).integers(-3000, 3000, size=(n, p)).astype(np.float64)
+    x[:, p - 1] = np.random.default_rng(p + 1).standard_normal(n) * 7.0 + 1e4
+    is_int = [True] * (p - 1) + [False]
+    h = L.stats_open(aos_config(p, is_int, ident=(), stream=current_stream(), block_rows=1024,
+                                precision=L.STATS_PREC_FP64))
+    try:
+        L.stats_accumulate(h, [to_dev(x)], n)
+        raw = L.stats_raw(h, p)
+        fin = L.stats_finalize(h, p)
+    finally:
+        L.stats_close(h)
+    st = oracle.sufficient_stats(oracle.columns_of(x), is_int, threads=8)
+    check_raw_against_oracle(raw, st, is_int)
+    check_final_against_oracle(fin, oracle.finalize(st), is_int)
