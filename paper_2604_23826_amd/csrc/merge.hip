@@ -16,9 +16,11 @@
 //    This never subtracts X^T X and n mu mu^T (section "Numerical
 //    Considerations").
 //
-// Each entry (a column i, or a pair i <= j) is owned by one workgroup or
-// thread that walks the partial results in a fixed order, so the result is
-// deterministic.  The column means needed by a pair are recomputed by the
+// Each entry (a column i, or a pair i <= j) is folded in a fixed order: by
+// one workgroup or thread over all partial results, or, for launches with
+// many block records, over fixed slices of them whose totals are then folded
+// in a fixed order (the slices depend only on the record count and p), so
+// the result is deterministic.  The column means needed by a pair are recomputed by the
 // pair's owner with the same operations as the column's owner, hence
 // bitwise equal.
 #include "common.hpp"
